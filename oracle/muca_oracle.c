@@ -358,6 +358,9 @@ int orc_run(const orc_system *s, const orc_weights *w, const orc_moves *mv, uint
                 double delta[3];
                 for (int a = 0; a < 3; ++a) delta[a] = mv->trans_max * (2.0 * u01(r1[1 + a]) - 1.0);
                 double before = inter_terms_of_chain(s, pos, ch);
+                int c0 = s->chain_start[ch], nc = s->chain_start[ch + 1] - c0;
+                double *keep = (double *)malloc(sizeof(double) * 3 * (size_t)nc);
+                memcpy(keep, pos + 3 * c0, sizeof(double) * 3 * (size_t)nc);
                 for (int i = s->chain_start[ch]; i < s->chain_start[ch + 1]; ++i)
                     for (int a = 0; a < 3; ++a) pos[3 * i + a] += delta[a];
                 double after = inter_terms_of_chain(s, pos, ch);
@@ -366,10 +369,10 @@ int orc_run(const orc_system *s, const orc_weights *w, const orc_moves *mv, uint
                 int acc = metropolis(w, e, k, e_new, u01(r2[0]), &k_new);
                 if (acc) { e = e_new; k = k_new; cnt->rigid_accepted++; }
                 else {
-                    for (int i = s->chain_start[ch]; i < s->chain_start[ch + 1]; ++i)
-                        for (int a = 0; a < 3; ++a) pos[3 * i + a] -= delta[a];
+                    memcpy(pos + 3 * c0, keep, sizeof(double) * 3 * (size_t)nc);
                     if (k_new < 0) cnt->window_rejects++;
                 }
+                free(keep);
                 cnt->rigid_moves++;
                 hist[k] += 1;
             }

@@ -1,0 +1,161 @@
+"""GPU parity of the MUCA sweep and weight update against the FP64 oracle, through the C ABI.
+
+FP64 mode: the same Philox streams give the same trajectories, so accept/reject sequences and
+histogram counts must agree bit for bit, coordinates and energies to rounding (1e-11 relative to
+the energy scale).  FP32-split mode: pair terms in FP32, so trajectories differ; the running
+energy of each walker must stay within 1e-5 of the sum of term magnitudes of the FP64 energy of
+its own coordinates."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1702_01770_amd as P
+    P.load()
+    return P
+
+
+def _oracle_walkers(orc, wl, sys_index, walkers, n_sweeps, weights=None, log_moves=0,
+                    first_walker=None):
+    sp = wl.systems[sys_index]
+    s = orc.System.from_workload(wl, sys_index)
+    pos0 = workloads.initial_positions(wl)[sys_index]
+    W = weights if weights is not None else orc.Weights(sp.e_lo, wl.bin_width, sp.n_bins)
+    H = np.zeros(sp.n_bins, np.uint64)
+    out = []
+    base = sys_index * walkers if first_walker is None else first_walker
+    for i in range(walkers):
+        w = orc.Walker(s, pos0, base + i, wl.seed)
+        log = np.zeros(log_moves, np.uint8) if log_moves else None
+        w.run(W, orc.move_params(wl), n_sweeps, H, accept_log=log)
+        out.append((w, log))
+    return H, out
+
+
+def _compare(lib, orc, wl, walkers, n_sweeps, weights_by_sys=None, log_moves=None):
+    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=walkers, precision=0)
+    if weights_by_sys:
+        for s, Wt in weights_by_sys.items():
+            m.set_weights(s, Wt.beta, Wt.alpha, Wt.g)
+    n_log = log_moves if log_moves is not None else n_sweeps * min(x.n_beads for x in wl.systems)
+    m.set_accept_log(n_log)
+    m.sweep(n_sweeps)
+    for s in range(wl.n_systems):
+        sp = wl.systems[s]
+        Wt = weights_by_sys.get(s) if weights_by_sys else None
+        H, ows = _oracle_walkers(orc, wl, s, walkers, n_sweeps, Wt, log_moves=n_log)
+        Hg = m.histogram(s)
+        log_g = m.accept_log(s)
+        pos_g, e_g, cnt = m.walkers_state(s)
+        print(f"system {s}: N={sp.n_beads} moves={int(H.sum())}")
+        assert np.array_equal(Hg, H), "histograms differ"
+        for i, (ow, olog) in enumerate(ows):
+            assert np.array_equal(log_g[i], olog), f"accept sequence of walker {i} differs"
+            _, _, scale = orc.System.from_workload(wl, s).energy_parts(ow.pos)
+            assert np.allclose(pos_g[i], ow.pos, rtol=0, atol=1e-10)
+            assert e_g[i] == pytest.approx(ow.energy, abs=1e-11 * max(1.0, scale))
+            assert cnt["moves"][i] == ow.counters.moves
+            assert cnt["accepted"][i] == ow.counters.accepted
+            assert cnt["rigid_moves"][i] == ow.counters.rigid_moves
+            assert cnt["rigid_accepted"][i] == ow.counters.rigid_accepted
+            assert cnt["window_rejects"][i] == ow.counters.window_rejects
+            assert cnt["sweeps"][i] == n_sweeps
+    m.close()
+
+
+def test_fp64_single_chain_flat_weights(lib, orc):
+    wl = workloads.single_chain()
+    _compare(lib, orc, wl, walkers=1, n_sweeps=3000)
+
+
+def test_fp64_single_chain_muca_weights_several_walkers(lib, orc):
+    wl = workloads.single_chain()
+    res = orc.muca(wl, n_iter=4, n_sweeps=4000, walkers=2)
+    _compare(lib, orc, wl, walkers=6, n_sweeps=1500, weights_by_sys={0: res["weights"]})
+
+
+def test_fp64_batched_uneven_lengths(lib, orc):
+    wl = workloads.batched_chains(n_seq=3, n_min=13, n_max=60)
+    _compare(lib, orc, wl, walkers=3, n_sweeps=300)
+
+
+def test_fp64_aggregation_periodic_rigid(lib, orc):
+    wl = workloads.aggregation()
+    _compare(lib, orc, wl, walkers=3, n_sweeps=400)
+
+
+def test_fp64_cross_seeding_two_slots_torsion(lib, orc):
+    wl = workloads.cross_seeding()
+    _compare(lib, orc, wl, walkers=2, n_sweeps=200)
+
+
+def test_weight_update_matches_oracle(lib, orc):
+    wl = workloads.single_chain()
+    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=4, precision=0)
+    W = orc.Weights(wl.systems[0].e_lo, wl.bin_width, wl.systems[0].n_bins)
+    for it in range(3):
+        m.sweep(2000)
+        H = m.histogram(0)
+        st = m.update_weights()[0]
+        W.berg_update(H)
+        b, a, g = m.weights(0)
+        assert np.array_equal(m.histogram(0, last=True), H)
+        assert not m.histogram(0).any()
+        assert np.allclose(b, W.beta, rtol=1e-13, atol=1e-12)
+        assert np.allclose(g, W.g, rtol=1e-14, atol=0)
+        assert np.allclose(a, W.alpha, rtol=1e-12, atol=1e-9)
+        cv, pk, lo, hi = orc.flatness(H)
+        assert st["iteration"] == it and st["moves"] == int(H.sum())
+        assert (st["k_min"], st["k_max"]) == (lo, hi)
+        assert st["cvar"] == pytest.approx(cv, rel=1e-12) and st["max_peak"] == pytest.approx(pk, rel=1e-12)
+        # the oracle continues from the GPU's weights so the next histogram is comparable
+        W = orc.Weights(W.e_lo, W.bin_width, W.n_bins, b, a, g)
+    m.close()
+
+
+@pytest.mark.parametrize("make", [lambda: workloads.batched_chains(n_seq=4, walkers=32),
+                                  lambda: workloads.aggregation(walkers=16),
+                                  lambda: workloads.cross_seeding(walkers=16)])
+def test_fp32_split_energy_accuracy(lib, orc, make):
+    wl = make()
+    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), precision=1, resync_sweeps=0)
+    m.sweep(400)
+    for s in range(wl.n_systems):
+        sysd = orc.System.from_workload(wl, s)
+        pos, e, cnt = m.walkers_state(s)
+        for i in range(pos.shape[0]):
+            e64, _, scale = sysd.energy_parts(pos[i])
+            assert abs(e[i] - e64) <= 1e-5 * scale, (s, i, e[i], e64, scale)
+        assert np.all(cnt["accepted"] > 0.05 * cnt["moves"])
+        bl = np.linalg.norm(np.diff(pos, axis=1), axis=2)
+        starts = np.cumsum([0] + wl.systems[s].chain_len)[:-1]
+        keep = np.ones(bl.shape[1], bool)
+        keep[starts[1:] - 1] = False                     # skip links between chains
+        assert np.max(np.abs(bl[:, keep] - 1.0)) < 1e-12
+    m.close()
+
+
+def test_fp32_resync_drift_and_iterate_graph(lib, orc):
+    wl = workloads.aggregation(walkers=64)
+    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), precision=1,
+                               resync_sweeps=50, drift_tol=1e-3)
+    m.iterate(200, 3)
+    hist = m.stats_history(0, 3)
+    assert np.all(hist[:, 0, 0] == 64 * 200 * (36 + 1))        # every trial move counted
+    pos, e, cnt = m.walkers_state(0)
+    assert np.all(cnt["sweeps"] == 600) and np.all(cnt["max_drift"] < 1e-4)
+    m.close()
+
+
+def test_window_error_is_reported(lib):
+    wl = workloads.single_chain()
+    sp = wl.systems[0]
+    sp.e_lo = 10.0                                       # window above the starting energy
+    with pytest.raises(lib.MucaError) as ei:
+        lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=1)
+    assert "WINDOW" in str(ei.value)
