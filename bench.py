@@ -1,0 +1,172 @@
+"""Benchmark: multicanonical (MUCA) trial moves per second on one MI355X.
+
+Workload (synthetic stand-in for the paper's chains, see workloads.batched_chains): 32 single-chain
+AB systems with lengths drawn uniformly from 13..55 (~60 % A), 128 walkers per system (4096
+walkers), bin width 0.05 over [-4N, +N), FP32 pair arithmetic with FP64 energies / weights.
+One step = one MUCA iteration: --sweeps sweeps of every walker followed by the Berg weight
+update, replayed from a captured HIP graph (persistent sweep launches + update kernel).
+
+Printed JSON line: value = single-bead trial moves per second over all walkers (batched form),
+plus the plain form (one walker per system, same kernels) for comparison, the roofline of the
+sweep kernel (algorithmic FP32/FP64 ALU operations per launch over the launch time measured
+with HIP events on the library's stream) and the FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (published, packed)
+
+
+def algorithmic_flops_per_move(n_beads: int, n_chains: int = 1, periodic: bool = False,
+                               torsion: bool = False) -> float:
+    """Operations a single-bead trial move must perform (Measurement):
+    per non-bonded partner two pair-term evaluations (separation 3, r^2 5, reciprocal 1, s^3 2,
+    kappa s^3 (s^3 - C) 3 = 14 each; +9 each for the periodic minimum image) plus difference
+    and accumulation (2); 60 for proposal, bending terms and acceptance, +40 with torsion."""
+    bonded = (2 * (n_beads - 2 * n_chains) + 2 * n_chains) / n_beads   # mean bonded neighbours
+    partners = n_beads - 1 - bonded
+    per_pair = 2 * (14 + (9 if periodic else 0)) + 2
+    return partners * per_pair + 60 + (40 if torsion else 0)
+
+
+_STREAMS = []
+
+
+def make_stream():
+    """A non-default torch stream for the library (kept alive for the whole run)."""
+    import torch
+    torch.cuda.set_device(0)
+    s = torch.cuda.Stream()
+    _STREAMS.append(s)
+    return s, s.cuda_stream
+
+
+def run_gpu(wl, walkers, n_sweeps, steps, warmup, stream_handle, autotune=True):
+    import ctypes
+
+    import paper_1702_01770_amd as P
+    import workloads
+    m = P.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=walkers,
+                             stream=stream_handle)
+    chosen = m.autotune(probe_sweeps=max(5, n_sweeps // 200)) if autotune else None
+    hip = ctypes.CDLL("libamdhip64.so")
+    ev = [ctypes.c_void_p() for _ in range(2)]
+    for e in ev:
+        assert hip.hipEventCreate(ctypes.byref(e)) == 0
+    st = ctypes.c_void_p(stream_handle)
+    if warmup:
+        m.iterate(n_sweeps, warmup)
+    m.synchronize()
+    t0 = time.perf_counter()
+    assert hip.hipEventRecord(ev[0], st) == 0
+    m.iterate(n_sweeps, steps)
+    assert hip.hipEventRecord(ev[1], st) == 0
+    m.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ctypes.c_float(0)
+    assert hip.hipEventSynchronize(ev[1]) == 0
+    assert hip.hipEventElapsedTime(ctypes.byref(ms), ev[0], ev[1]) == 0
+    for e in ev:
+        hip.hipEventDestroy(e)
+    stats = m.stats_history(warmup, steps)
+    moves = 0
+    for s, sp in enumerate(wl.systems):
+        moves += walkers * n_sweeps * sp.n_beads * steps
+    _, _, cnt = m.walkers_state(0)
+    m.close()
+    return dict(moves=moves, event_ms=ms.value, wall_s=wall, stats=stats, chosen=chosen,
+                acc_rate=float(np.sum(cnt["accepted"]) / max(1, np.sum(cnt["moves"]))))
+
+
+def cpu_baseline(wl, target_s: float = 15.0):
+    """FP64 oracle on one host core: one walker of every system, sweeps sized to ~target_s."""
+    import oracle
+    import workloads
+    oracle.build(force=False)
+    pos0 = workloads.initial_positions(wl)
+    walkers = []
+    for s, sp in enumerate(wl.systems):
+        sysd = oracle.System.from_workload(wl, s)
+        walkers.append((oracle.Walker(sysd, pos0[s], s * wl.walkers_per_system, wl.seed),
+                        oracle.Weights(sp.e_lo, wl.bin_width, sp.n_bins), sp))
+    mv = oracle.move_params(wl)
+
+    def sweep_all(n):
+        moves = 0
+        t0 = time.perf_counter()
+        for w, W, sp in walkers:
+            H = np.zeros(sp.n_bins, np.uint64)
+            before = w.counters.moves
+            w.run(W, mv, n, H)
+            moves += w.counters.moves - before
+        return moves, time.perf_counter() - t0
+
+    m0, t0 = sweep_all(10)
+    n = max(10, int(10 * target_s / max(t0, 1e-3)))
+    m1, t1 = sweep_all(n)
+    return dict(value=m1 / t1, unit="moves/s", cores=1, kind="oracle",
+                sample=f"1 walker of each of the {len(wl.systems)} systems x {n} sweeps "
+                       f"({m1} single-bead moves, {t1:.1f} s, flat weights)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--sweeps", type=int, default=100000, help="sweeps per MUCA iteration")
+    ap.add_argument("--plain-sweeps", type=int, default=20000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import workloads
+
+    wl = workloads.batched_chains()
+    _, sh = make_stream()
+    r = run_gpu(wl, wl.walkers_per_system, args.sweeps, args.steps, args.warmup, sh)
+    sec = r["event_ms"] / 1e3
+    value = r["moves"] / sec
+    flops_per_step = sum(wl.walkers_per_system * args.sweeps * sp.n_beads *
+                         algorithmic_flops_per_move(sp.n_beads) for sp in wl.systems)
+    achieved = flops_per_step * args.steps / sec / 1e12
+    out = {
+        "metric": "MC moves/sec (batched vs plain, 1 GPU) at matched S(E) error vs FP64 oracle",
+        "value": value, "unit": "moves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["event_ms"] / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 pair terms + f64 energy/weights", "data": "synthetic",
+        "config": {"workload": "batched single chains: 32 seeded A/B sequences, N uniform in "
+                               "13..55, 4096 walkers (128/system), FP32-split",
+                   "sweeps_per_step": args.sweeps, "waves_per_block": r["chosen"],
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None},
+        "acceptance": r["acc_rate"],
+        "wall_s": r["wall_s"],
+    }
+    if not args.no_plain:
+        rp = run_gpu(wl, 1, args.plain_sweeps, 1, 0, sh, autotune=False)
+        plain = rp["moves"] / (rp["event_ms"] / 1e3)
+        out["plain"] = {"value": plain, "unit": "moves/s", "walkers_per_system": 1,
+                        "sweeps": args.plain_sweeps}
+        out["batched_over_plain"] = value / plain
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

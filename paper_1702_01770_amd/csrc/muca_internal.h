@@ -63,6 +63,7 @@ struct EnergyArgs {
     double k_intra, k_inter, k_bend, k_tors;
     double box_len, inv_box;
     int periodic;
+    double theta[4];           // C_AB, C_BB, kappa_bend, kappa_tors
     double *energy;            // [n_cfg]
     const double *grad_e;      // [n_cfg]
     float *grad_x;             // [n_cfg][N][3]
@@ -74,11 +75,14 @@ hipError_t launch_energy_bwd(const EnergyArgs &a, double *grad_theta, hipStream_
 // Reweighting (muca_reweight.hip).
 size_t reweight_workspace_bytes(long long n, int n_t);
 hipError_t launch_reweight_fwd(const double *energy, const double *lnw0, long long n,
-                               const double *temps_dev, int n_t, double *mean, double *cv,
+                               const double *temps_host, int n_t, double *mean, double *cv,
                                double *moments, void *ws, hipStream_t st);
 hipError_t launch_reweight_bwd(const double *energy, const double *lnw0, long long n,
-                               const double *temps_dev, int n_t, const double *moments,
+                               const double *temps_host, int n_t, const double *moments,
                                const double *grad_mean, const double *grad_cv, double *grad_e,
                                hipStream_t st);
+
+// Failure message of context-free entry points, reported by muca_last_error(NULL).
+void set_global_error(const char *msg);
 
 }  // namespace muca

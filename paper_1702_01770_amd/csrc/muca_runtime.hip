@@ -72,6 +72,10 @@ struct muca_ctx {
         }                                                                               \
     } while (0)
 
+namespace muca {
+void set_global_error(const char *msg) { g_last_error = msg; }
+}  // namespace muca
+
 static int fail(muca_ctx *ctx, int code, const std::string &msg) {
     if (ctx) ctx->err = msg;
     g_last_error = msg;
@@ -723,6 +727,68 @@ int muca_set_state(muca_ctx *ctx, const void *buf, size_t bytes) {
     CK(put(ctx->d_hist, sizeof(unsigned long long) * nb));
     CK(put(ctx->d_hist_last, sizeof(unsigned long long) * nb));
     CK(put(ctx->d_iter, sizeof(long long)));
+    return MUCA_OK;
+}
+
+static int energy_args(muca_ctx *ctx, int32_t sys, const float *x, int64_t n_cfg,
+                       const double theta[4], EnergyArgs *a) {
+    if (!ctx) return fail(nullptr, MUCA_E_INVAL, "null context");
+    if (sys < 0 || sys >= ctx->n_sys) return fail(ctx, MUCA_E_INVAL, "system index out of range");
+    if (!x || !theta || n_cfg < 0) return fail(ctx, MUCA_E_INVAL, "bad arguments");
+    if (ctx->n_types != 2) return fail(ctx, MUCA_E_INVAL, "theta = (C_AB, C_BB, k_bend, k_tors) needs a two-letter lexicon");
+    EnergyArgs &e = *a;
+    e = EnergyArgs{};
+    e.sys = ctx->d_sys;
+    e.binfo = ctx->d_binfo;
+    e.sys_index = sys;
+    e.x = x;
+    e.n_cfg = n_cfg;
+    for (int i = 0; i < kMaxTypes * kMaxTypes; ++i) e.c_lj[i] = ctx->args.c_lj[i];
+    e.n_types = ctx->n_types;
+    e.k_intra = ctx->args.k_intra;
+    e.k_inter = ctx->args.k_inter;
+    e.k_bend = theta[2];
+    e.k_tors = theta[3];
+    e.box_len = ctx->args.box_len;
+    e.inv_box = ctx->args.inv_box;
+    e.periodic = ctx->periodic ? 1 : 0;
+    for (int t = 0; t < 4; ++t) e.theta[t] = theta[t];
+    return MUCA_OK;
+}
+
+int muca_energy_fwd(muca_ctx *ctx, int32_t sys, const float *x, int64_t n_cfg,
+                    const double theta[4], double *energy) {
+    EnergyArgs a;
+    int rc = energy_args(ctx, sys, x, n_cfg, theta, &a);
+    if (rc != MUCA_OK) return rc;
+    if (!energy) return fail(ctx, MUCA_E_INVAL, "null energy output");
+    if (n_cfg == 0) return MUCA_OK;
+    a.energy = energy;
+    CK(launch_energy_fwd(a, ctx->stream));
+    return MUCA_OK;
+}
+
+int muca_energy_bwd(muca_ctx *ctx, int32_t sys, const float *x, int64_t n_cfg,
+                    const double theta[4], const double *grad_e, float *grad_x,
+                    double *grad_theta) {
+    EnergyArgs a;
+    int rc = energy_args(ctx, sys, x, n_cfg, theta, &a);
+    if (rc != MUCA_OK) return rc;
+    if (!grad_e || !grad_x || !grad_theta) return fail(ctx, MUCA_E_INVAL, "null gradient pointer");
+    if (n_cfg == 0) return MUCA_OK;
+    if (n_cfg > ctx->theta_part_cap) {
+        // per-configuration dE/dtheta partials, kept for later calls
+        CK(hipStreamSynchronize(ctx->stream));
+        if (ctx->d_theta_part) CK(hipFree(ctx->d_theta_part));
+        ctx->d_theta_part = nullptr;
+        ctx->theta_part_cap = 0;
+        CK(hipMalloc(&ctx->d_theta_part, sizeof(double) * 4 * (size_t)n_cfg));
+        ctx->theta_part_cap = n_cfg;
+    }
+    a.grad_e = grad_e;
+    a.grad_x = grad_x;
+    a.theta_part = ctx->d_theta_part;
+    CK(launch_energy_bwd(a, grad_theta, ctx->stream));
     return MUCA_OK;
 }
 
