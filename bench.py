@@ -48,44 +48,97 @@ def make_stream():
     torch.cuda.set_device(0)
     s = torch.cuda.Stream()
     _STREAMS.append(s)
-    return s, s.cuda_stream
+    return s
 
 
-def run_gpu(wl, walkers, n_sweeps, steps, warmup, stream_handle, autotune=True):
-    import ctypes
+def run_gpu(wl, walkers, n_sweeps, steps, warmup, stream, autotune=True):
+    """Run `warmup` then `steps` MUCA iterations; time the steps with HIP events recorded on the
+    stream the library launches on."""
+    import torch
 
     import paper_1702_01770_amd as P
     import workloads
     m = P.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=walkers,
-                             stream=stream_handle)
+                             stream=stream.cuda_stream)
     chosen = m.autotune(probe_sweeps=max(5, n_sweeps // 200)) if autotune else None
-    hip = ctypes.CDLL("libamdhip64.so")
-    ev = [ctypes.c_void_p() for _ in range(2)]
-    for e in ev:
-        assert hip.hipEventCreate(ctypes.byref(e)) == 0
-    st = ctypes.c_void_p(stream_handle)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
     if warmup:
         m.iterate(n_sweeps, warmup)
     m.synchronize()
     t0 = time.perf_counter()
-    assert hip.hipEventRecord(ev[0], st) == 0
+    e0.record(stream)
     m.iterate(n_sweeps, steps)
-    assert hip.hipEventRecord(ev[1], st) == 0
+    e1.record(stream)
     m.synchronize()
+    e1.synchronize()
     wall = time.perf_counter() - t0
-    ms = ctypes.c_float(0)
-    assert hip.hipEventSynchronize(ev[1]) == 0
-    assert hip.hipEventElapsedTime(ctypes.byref(ms), ev[0], ev[1]) == 0
-    for e in ev:
-        hip.hipEventDestroy(e)
+    ms = e0.elapsed_time(e1)
     stats = m.stats_history(warmup, steps)
     moves = 0
     for s, sp in enumerate(wl.systems):
         moves += walkers * n_sweeps * sp.n_beads * steps
     _, _, cnt = m.walkers_state(0)
     m.close()
-    return dict(moves=moves, event_ms=ms.value, wall_s=wall, stats=stats, chosen=chosen,
+    return dict(moves=moves, event_ms=ms, wall_s=wall, stats=stats, chosen=chosen,
                 acc_rate=float(np.sum(cnt["accepted"]) / max(1, np.sum(cnt["moves"]))))
+
+
+def matched_error(stream):
+    """Batched vs plain at the same statistics per MUCA iteration, on the 6-bead chain whose
+    FP64-oracle replica statistics are stored in tests/golden/muca_n6_reference.json.  Plain: one
+    walker doing all sweeps of an iteration; batched: 64 walkers sharing the weights, each doing
+    1/64 of them.  Reports the S(E) error of each against the oracle replica mean (RMS over the
+    grid, in units of the oracle's replica standard deviation) and the GPU time of each run."""
+    import torch
+
+    import paper_1702_01770_amd as P
+    import workloads
+    ref = json.load(open(os.path.join(ROOT, "tests", "golden", "muca_n6_reference.json")))
+    oS = np.array([c["S"] for c in ref["curves"]])
+    o_mean, o_sd = oS.mean(axis=0), oS.std(axis=0, ddof=1)
+    total = ref["walkers"] * ref["sweeps"]
+    iters, block, k_lo, k_hi = ref["iterations"], ref["block"], ref["k_lo"], ref["k_hi"]
+    out = {}
+    for name, walkers in (("plain", 1), ("batched", 64)):
+        wl = workloads.single_chain(n=6)
+        sp = wl.systems[0]
+        reps = 4
+        wl.systems = [sp] * reps                       # 4 independent replicas at once
+        m = P.Muca.from_workload(wl, workloads.initial_positions(workloads.single_chain(n=6)) * reps,
+                                 walkers=walkers, precision=1, seed=77_000_003,
+                                 stream=stream.cuda_stream)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        bs = [[] for _ in range(reps)]
+        al = [[] for _ in range(reps)]
+        ms_total = 0.0
+        for _ in range(iters):
+            e0.record(stream)
+            m.sweep(total // walkers)
+            e1.record(stream)
+            m.update_weights()
+            e1.synchronize()
+            ms_total += e0.elapsed_time(e1)
+            for r in range(reps):
+                b, a, _ = m.weights(r)
+                bs[r].append(b)
+                al[r].append(a)
+        m.close()
+        errs = []
+        for r in range(reps):
+            res = P.microcanonical_analyze(np.array(bs[r]), np.array(al[r]), sp.e_lo,
+                                           wl.bin_width, k_lo, k_hi, iters - block, iters,
+                                           block, wl.bin_width, beta_c=1.0)
+            d = (res["S"] - o_mean)[:-1] / o_sd[:-1]
+            errs.append(float(np.sqrt(np.mean(d * d))))
+        out[name] = {"walkers": walkers, "sweeps_per_walker_per_iter": total // walkers,
+                     "gpu_ms_per_iter": ms_total / iters,
+                     "S_rms_err_in_oracle_sd": float(np.mean(errs))}
+    out["time_ratio_plain_over_batched"] = (out["plain"]["gpu_ms_per_iter"] /
+                                            out["batched"]["gpu_ms_per_iter"])
+    out["system"] = "single chain N=6 (workloads.single_chain(n=6)), 4 replicas per form"
+    return out
 
 
 def cpu_baseline(wl, target_s: float = 15.0):
@@ -128,6 +181,7 @@ def main():
     ap.add_argument("--plain-sweeps", type=int, default=20000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-matched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -135,8 +189,8 @@ def main():
     import workloads
 
     wl = workloads.batched_chains()
-    _, sh = make_stream()
-    r = run_gpu(wl, wl.walkers_per_system, args.sweeps, args.steps, args.warmup, sh)
+    st = make_stream()
+    r = run_gpu(wl, wl.walkers_per_system, args.sweeps, args.steps, args.warmup, st)
     sec = r["event_ms"] / 1e3
     value = r["moves"] / sec
     flops_per_step = sum(wl.walkers_per_system * args.sweeps * sp.n_beads *
@@ -158,11 +212,13 @@ def main():
         "wall_s": r["wall_s"],
     }
     if not args.no_plain:
-        rp = run_gpu(wl, 1, args.plain_sweeps, 1, 0, sh, autotune=False)
+        rp = run_gpu(wl, 1, args.plain_sweeps, 1, 0, st, autotune=False)
         plain = rp["moves"] / (rp["event_ms"] / 1e3)
         out["plain"] = {"value": plain, "unit": "moves/s", "walkers_per_system": 1,
                         "sweeps": args.plain_sweeps}
         out["batched_over_plain"] = value / plain
+    if not args.no_matched:
+        out["matched_error"] = matched_error(st)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out))

@@ -166,9 +166,11 @@ int muca_get_accept_log(muca_ctx *ctx, int32_t sys, uint8_t *out, int64_t n_move
 int muca_get_state(muca_ctx *ctx, void *buf, size_t *bytes);
 int muca_set_state(muca_ctx *ctx, const void *buf, size_t bytes);
 
-/* Time a few candidate walkers-per-workgroup settings on probe_sweeps sweeps, keep the fastest
- * and restore the sampling state, so results do not depend on tuning.  *chosen (host, may be
- * NULL) receives the setting. */
+/* Time the candidate workgroup schedules (walkers per workgroup 16, 8, 4, 2, 1; with several
+ * systems, with and without pairing long and short chains in one workgroup) on probe_sweeps
+ * sweeps, keep the fastest and restore the sampling state, so results do not depend on tuning
+ * (every walker's trajectory is independent of the schedule).  *chosen (host, may be NULL)
+ * receives the walkers per workgroup, negated for an unpaired schedule. */
 int muca_autotune(muca_ctx *ctx, int64_t probe_sweeps, int32_t *chosen);
 
 /*

@@ -77,6 +77,12 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() or "
                            "python paper_1702_01770_amd/build.py")
+    try:
+        # torch ships its own HIP runtime under the same soname; loading it first makes the
+        # library bind to that single runtime, so torch streams and allocations are shared
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     L.muca_init.argtypes = [C.POINTER(MucaConfig), C.POINTER(vp)]

@@ -19,6 +19,10 @@
 #include "../../include/muca.h"
 #include "muca_internal.h"
 
+// The analysis is cheap; keep every multiply and add separately rounded so that results follow
+// the reference evaluation order exactly (the curvature S'' is ill-conditioned near C_V poles).
+#pragma clang fp contract(off)
+
 namespace muca {
 
 __device__ __forceinline__ double s_at(const double *beta, const double *alpha, int K, double e_lo,
@@ -80,16 +84,16 @@ __global__ void k_curves(AnalysisDev d) {
         vb += (beta - mb) * (beta - mb);
         vc += (cv - mc) * (cv - mc);
     }
-    const double se = nb > 1 ? 1.0 / sqrt((double)nb) : 0.0;
+    const double rnb = sqrt((double)nb);
     const double den = nb > 1 ? (double)(nb - 1) : 1.0;
     double *o = d.out;
     o[0 * G + g] = e / N;
     o[1 * G + g] = ms;
-    o[2 * G + g] = nb > 1 ? sqrt(vs / den) * se : 0.0;
+    o[2 * G + g] = nb > 1 ? sqrt(vs / den) / rnb : 0.0;
     o[3 * G + g] = mb;
-    o[4 * G + g] = nb > 1 ? sqrt(vb / den) * se : 0.0;
+    o[4 * G + g] = nb > 1 ? sqrt(vb / den) / rnb : 0.0;
     o[5 * G + g] = mc;
-    o[6 * G + g] = nb > 1 ? sqrt(vc / den) * se : 0.0;
+    o[6 * G + g] = nb > 1 ? sqrt(vc / den) / rnb : 0.0;
     const int n_samples = nb > 1 ? nb + 1 : 1;
     for (int smp = 0; smp < n_samples; ++smp) {
         double S0, Sm, Sp;

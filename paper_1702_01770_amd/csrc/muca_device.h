@@ -28,9 +28,18 @@ struct SysDev {
     int chain_start[kMaxBeads / 3 + 2];   // chains of >= 3 beads: at most 42 chains
 };
 
-// One entry per workgroup of the sweep launch: which system and which walkers it runs.
+// One entry per workgroup of the sweep launch.  A workgroup runs up to 16 walkers (one per
+// wave) drawn from at most kMaxWgSys systems; each system's ln W table and histogram sit in LDS
+// at bin offset lds_off[i].  Mixing long and short chains in one workgroup evens out the work
+// of the four SIMDs of a compute unit.
+constexpr int kMaxWgSys = 4;
+constexpr int kMaxWgWaves = 16;
 struct WorkItem {
-    int sys, w_begin, w_count, pad;
+    int n_sys;
+    int sys[kMaxWgSys];
+    int lds_off[kMaxWgSys];
+    int walker[kMaxWgWaves];   // walker id of each wave, -1 = idle wave
+    int slot[kMaxWgWaves];     // index into sys[] of each wave
 };
 
 // Counter slots per walker in WalkerDev::cnt.

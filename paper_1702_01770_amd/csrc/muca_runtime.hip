@@ -56,6 +56,8 @@ struct muca_ctx {
     IterStatsDev *d_stats = nullptr;
     int stats_cap = 4096;
     int wpb = 16, n_items = 0;
+    bool paired = true;
+    size_t lds_limit = 0;
     size_t lds_bytes = 0;
     int chunk_sweeps = 1000;
     std::map<long long, hipGraphExec_t> graphs;
@@ -107,24 +109,81 @@ static void drop_graphs(muca_ctx *ctx) {
     ctx->graphs.clear();
 }
 
-// Workgroup schedule: each workgroup runs up to wpb walkers of one system (so that system's
-// ln W table and histogram can live in LDS); workgroups of the longest chains come first.
-static int build_schedule(muca_ctx *ctx, int wpb) {
+static size_t lds_for_bins(long long bins) {
+    return (size_t)bins * (sizeof(double) * 2 + sizeof(unsigned int)) +
+           sizeof(double) * kMaxTypes * kMaxTypes;
+}
+
+// Workgroup schedule.  A workgroup runs wpb walkers, one per wave; waves w, w+4, w+8, w+12
+// share SIMD w % 4.  The cost of a walker is proportional to its chain length (trial moves per
+// sweep), so when several systems are sampled, the longest remaining system is paired with the
+// shortest one whose LDS tables fit beside it, and their walkers are interleaved so that every
+// SIMD gets half of each: long and short chains then finish together.  Workgroups of the
+// longest chains are listed first.
+static int build_schedule(muca_ctx *ctx, int wpb, bool pair) {
+    const int dev_lds = (int)ctx->lds_limit;
     std::vector<WorkItem> items;
     std::vector<int> order(ctx->n_sys);
     for (int s = 0; s < ctx->n_sys; ++s) order[s] = s;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         return ctx->sys[a].n_beads > ctx->sys[b].n_beads;
     });
-    for (int s : order)
-        for (int w0 = 0; w0 < ctx->W; w0 += wpb)
-            items.push_back(WorkItem{s, ctx->sys[s].walker_off + w0, std::min(wpb, ctx->W - w0), 0});
+    std::vector<int> next(ctx->n_sys, 0);      // next unscheduled walker of each system
+    auto blank = []() {
+        WorkItem w{};
+        w.n_sys = 0;
+        for (int i = 0; i < kMaxWgWaves; ++i) { w.walker[i] = -1; w.slot[i] = 0; }
+        return w;
+    };
+    size_t lds_max = 0;
+    int lo = 0, hi = ctx->n_sys - 1;
+    while (lo <= hi) {
+        const int A = order[lo], B = order[hi];
+        const bool can_pair = pair && wpb >= 8 && lo < hi &&
+            lds_for_bins((long long)ctx->sys[A].n_bins + ctx->sys[B].n_bins) <= (size_t)dev_lds;
+        if (!can_pair) {
+            // single-system workgroups for the rest of A
+            while (next[A] < ctx->W) {
+                WorkItem w = blank();
+                w.n_sys = 1; w.sys[0] = A; w.lds_off[0] = 0;
+                for (int v = 0; v < wpb && next[A] < ctx->W; ++v)
+                    w.walker[v] = ctx->sys[A].walker_off + next[A]++;
+                items.push_back(w);
+            }
+            lds_max = std::max(lds_max, lds_for_bins(ctx->sys[A].n_bins));
+            ++lo;
+            continue;
+        }
+        const int half = wpb / 2;
+        while (next[A] < ctx->W && next[B] < ctx->W) {
+            WorkItem w = blank();
+            w.n_sys = 2;
+            w.sys[0] = A; w.lds_off[0] = 0;
+            w.sys[1] = B; w.lds_off[1] = ctx->sys[A].n_bins;
+            // waves 0-3 and 8-11 run A, 4-7 and 12-15 run B (for wpb = 16; scaled for 8)
+            int na = 0, nb = 0;
+            for (int v = 0; v < wpb; ++v) {
+                const bool use_a = ((v / 4) % 2) == 0;
+                if (use_a && na < half && next[A] < ctx->W) {
+                    w.walker[v] = ctx->sys[A].walker_off + next[A]++; w.slot[v] = 0; ++na;
+                } else if (!use_a && nb < half && next[B] < ctx->W) {
+                    w.walker[v] = ctx->sys[B].walker_off + next[B]++; w.slot[v] = 1; ++nb;
+                }
+            }
+            items.push_back(w);
+        }
+        lds_max = std::max(lds_max, lds_for_bins((long long)ctx->sys[A].n_bins + ctx->sys[B].n_bins));
+        if (next[A] >= ctx->W) ++lo;
+        if (next[B] >= ctx->W) --hi;
+    }
     if (ctx->d_work) (void)hipFree(ctx->d_work);
     ctx->d_work = nullptr;
     CK(hipMalloc(&ctx->d_work, sizeof(WorkItem) * items.size()));
     CK(hipMemcpy(ctx->d_work, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice));
     ctx->n_items = (int)items.size();
     ctx->wpb = wpb;
+    ctx->paired = pair;
+    ctx->lds_bytes = lds_max;
     ctx->args.work = ctx->d_work;
     drop_graphs(ctx);
     return MUCA_OK;
@@ -440,7 +499,8 @@ int muca_init(const muca_config *cfg, muca_ctx **out) {
     wpb = std::min(wpb, ctx->W);
     // keep single launches short: about 2e5 trial moves per walker
     ctx->chunk_sweeps = std::max(1, 200000 / std::max(1, ctx->max_beads));
-    rc = build_schedule(ctx, wpb);
+    ctx->lds_limit = (size_t)dev_lds;
+    rc = build_schedule(ctx, wpb, true);
     if (rc != MUCA_OK) return bail(rc);
     *out = ctx;
     return MUCA_OK;
@@ -803,13 +863,17 @@ int muca_autotune(muca_ctx *ctx, int64_t probe_sweeps, int32_t *chosen) {
     if (rc != MUCA_OK) return rc;
     const int cands[] = {16, 8, 4, 2, 1};
     int best = ctx->wpb;
+    bool best_pair = ctx->paired;
     float best_ms = 1e30f;
     hipEvent_t e0, e1;
     CK(hipEventCreate(&e0));
     CK(hipEventCreate(&e1));
-    for (int c : cands) {
+    for (int ci = 0; ci < 10; ++ci) {
+        const int c = cands[ci % 5];
+        const bool pr = ci < 5;
         if (c > ctx->W) continue;
-        rc = build_schedule(ctx, c);
+        if (!pr && (ctx->n_sys == 1 || c < 8)) continue;   // pairing makes no difference
+        rc = build_schedule(ctx, c, pr);
         if (rc != MUCA_OK) break;
         rc = launch_chunked(ctx, 1);                 // warm the code path
         if (rc != MUCA_OK) break;
@@ -820,7 +884,7 @@ int muca_autotune(muca_ctx *ctx, int64_t probe_sweeps, int32_t *chosen) {
         CK(hipEventSynchronize(e1));
         float ms = 0.f;
         CK(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best_ms) { best_ms = ms; best = c; }
+        if (ms < best_ms) { best_ms = ms; best = c; best_pair = pr; }
         rc = muca_set_state(ctx, saved.data(), bytes);
         if (rc != MUCA_OK) break;
     }
@@ -829,9 +893,9 @@ int muca_autotune(muca_ctx *ctx, int64_t probe_sweeps, int32_t *chosen) {
     if (rc != MUCA_OK) return rc;
     rc = sync_and_check(ctx);
     if (rc != MUCA_OK) return rc;
-    rc = build_schedule(ctx, best);
+    rc = build_schedule(ctx, best, best_pair);
     if (rc != MUCA_OK) return rc;
-    if (chosen) *chosen = best;
+    if (chosen) *chosen = best_pair ? best : -best;
     return MUCA_OK;
 }
 

@@ -231,15 +231,15 @@ __device__ void run_walker(const SweepArgs &a, const SysDev &sd, int sys, int w,
                 const double vx = (xbx - xax) + a.cap_rho * rl_d(gxl, i);
                 const double vy = (xby - xay) + a.cap_rho * rl_d(gyl, i);
                 const double vz = (xbz - xaz) + a.cap_rho * rl_d(gzl, i);
-                const double nv = sqrt(vx * vx + vy * vy + vz * vz);
-                nx = xax + vx / nv; ny = xay + vy / nv; nz = xaz + vz / nv;
+                const double rv = rsqrt(vx * vx + vy * vy + vz * vz);
+                nx = xax + vx * rv; ny = xay + vy * rv; nz = xaz + vz * rv;
             } else {
                 const double xpx = bc_d(px, b - 1), xpy = bc_d(py, b - 1), xpz = bc_d(pz, b - 1);
                 const double xnx = bc_d(px, b + 1), xny = bc_d(py, b + 1), xnz = bc_d(pz, b + 1);
                 const double c = rl_d(cphi, i), sn = rl_d(sphi, i);
                 const double ax = xnx - xpx, ay = xny - xpy, az = xnz - xpz;
-                const double na = sqrt(ax * ax + ay * ay + az * az);
-                const double kx = ax / na, ky = ay / na, kz = az / na;
+                const double ra = rsqrt(ax * ax + ay * ay + az * az);
+                const double kx = ax * ra, ky = ay * ra, kz = az * ra;
                 const double vx = xbx - xpx, vy = xby - xpy, vz = xbz - xpz;
                 const double cx = ky * vz - kz * vy, cy = kz * vx - kx * vz, cz = kx * vy - ky * vx;
                 const double kv = kx * vx + ky * vy + kz * vz;
@@ -436,15 +436,19 @@ __device__ void run_walker(const SweepArgs &a, const SysDev &sd, int sys, int w,
 template <bool FP64, int SLOTS, bool PERIODIC>
 __global__ void __launch_bounds__(1024) k_sweep(SweepArgs a, long long n_sweeps) {
     extern __shared__ double2 lds_lnw[];
-    const WorkItem wi = a.work[blockIdx.x];
-    const SysDev &sd = a.sys[wi.sys];
-    const int K = sd.n_bins;
+    const WorkItem &wi = a.work[blockIdx.x];
+    const int ns = wi.n_sys;
+    const int total = wi.lds_off[ns - 1] + a.sys[wi.sys[ns - 1]].n_bins;   // bins in LDS
     double2 *lnw = lds_lnw;
-    double *ctab = reinterpret_cast<double *>(lds_lnw + K);            // C_LJ[t][t'], 4 x 4
+    double *ctab = reinterpret_cast<double *>(lds_lnw + total);        // C_LJ[t][t'], 4 x 4
     unsigned int *hist = reinterpret_cast<unsigned int *>(ctab + kMaxTypes * kMaxTypes);
-    for (int kk = threadIdx.x; kk < K; kk += blockDim.x) {
-        lnw[kk] = make_double2(a.beta[sd.bin_off + kk], a.alpha[sd.bin_off + kk]);
-        hist[kk] = 0u;
+    for (int i = 0; i < ns; ++i) {
+        const SysDev &sd = a.sys[wi.sys[i]];
+        const int off = wi.lds_off[i];
+        for (int kk = threadIdx.x; kk < sd.n_bins; kk += blockDim.x) {
+            lnw[off + kk] = make_double2(a.beta[sd.bin_off + kk], a.alpha[sd.bin_off + kk]);
+            hist[off + kk] = 0u;
+        }
     }
     if (threadIdx.x < kMaxTypes * kMaxTypes) {
         const int t = threadIdx.x / kMaxTypes, u = threadIdx.x % kMaxTypes;
@@ -452,12 +456,21 @@ __global__ void __launch_bounds__(1024) k_sweep(SweepArgs a, long long n_sweeps)
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6;
-    if (wave < wi.w_count)
-        run_walker<FP64, SLOTS, PERIODIC>(a, sd, wi.sys, wi.w_begin + wave, lnw, hist, ctab, n_sweeps);
+    const int w = wi.walker[wave];
+    if (w >= 0) {
+        const int i = wi.slot[wave];
+        const int off = wi.lds_off[i];
+        run_walker<FP64, SLOTS, PERIODIC>(a, a.sys[wi.sys[i]], wi.sys[i], w, lnw + off,
+                                          hist + off, ctab, n_sweeps);
+    }
     __syncthreads();
-    for (int kk = threadIdx.x; kk < K; kk += blockDim.x) {
-        const unsigned int h = hist[kk];
-        if (h) atomicAdd(&a.hist[sd.bin_off + kk], (unsigned long long)h);
+    for (int i = 0; i < ns; ++i) {
+        const SysDev &sd = a.sys[wi.sys[i]];
+        const int off = wi.lds_off[i];
+        for (int kk = threadIdx.x; kk < sd.n_bins; kk += blockDim.x) {
+            const unsigned int h = hist[off + kk];
+            if (h) atomicAdd(&a.hist[sd.bin_off + kk], (unsigned long long)h);
+        }
     }
 }
 
