@@ -61,8 +61,12 @@ enum { MUCA_PREC_FP64 = 0, MUCA_PREC_FP32_SPLIT = 1 };
  * precision: MUCA_PREC_FP64 evaluates everything in FP64; MUCA_PREC_FP32_SPLIT evaluates pair
  * terms in FP32 and keeps coordinates, the running energy, ln W and the recursion in FP64.
  * resync_sweeps > 0 recomputes every walker's energy in FP64 every resync_sweeps sweeps.
- * waves_per_block: walkers per workgroup (0 = library default); stream: a hipStream_t to run
- * on, or NULL for a stream created and owned by the context.
+ * waves_per_block: wavefronts per workgroup (0 = library default); walkers_per_wave: 1 runs
+ * one walker per 64-lane wavefront, 2 runs two walkers of a system in the two 32-lane halves of
+ * a wavefront (needs an even walkers_per_system and at most 8 waves per block), 0 lets the
+ * library choose (2 when possible).  Neither changes any result: every walker's trajectory
+ * depends only on its seed and walker index.  stream: a hipStream_t to run on, or NULL for a
+ * stream created and owned by the context.
  */
 typedef struct {
     int32_t n_systems;
@@ -86,8 +90,19 @@ typedef struct {
     double crank_max, cap_rho, trans_max;
     int32_t rigid_per_sweep;
     int32_t waves_per_block;
+    int32_t walkers_per_wave;
     void *stream;
 } muca_config;
+
+/* Launch plan of the sweep (muca_get_launch_info). */
+typedef struct {
+    int32_t walkers_per_wave;   /* 1 or 2 */
+    int32_t waves_per_block;
+    int32_t paired;             /* 1: workgroups mix a long and a short system */
+    int32_t workgroups;         /* workgroups per sweep launch */
+    int64_t lds_bytes;          /* dynamic LDS per workgroup */
+    int64_t sweeps_per_launch;  /* muca_sweep(n) issues ceil(n / sweeps_per_launch) launches */
+} muca_launch_info;
 
 /* Per-system statistics of one weight update (flatness as in Sec. 4.1). */
 typedef struct {
@@ -166,12 +181,16 @@ int muca_get_accept_log(muca_ctx *ctx, int32_t sys, uint8_t *out, int64_t n_move
 int muca_get_state(muca_ctx *ctx, void *buf, size_t *bytes);
 int muca_set_state(muca_ctx *ctx, const void *buf, size_t bytes);
 
-/* Time the candidate workgroup schedules (walkers per workgroup 16, 8, 4, 2, 1; with several
- * systems, with and without pairing long and short chains in one workgroup) on probe_sweeps
- * sweeps, keep the fastest and restore the sampling state, so results do not depend on tuning
- * (every walker's trajectory is independent of the schedule).  *chosen (host, may be NULL)
- * receives the walkers per workgroup, negated for an unpaired schedule. */
+/* Time the candidate sweep launches (one or two walkers per wave; 16, 8, 4, 2 or 1 waves per
+ * workgroup; with several systems, with and without pairing long and short chains in one
+ * workgroup) on probe_sweeps sweeps, keep the fastest and restore the sampling state, so
+ * results do not depend on tuning (every walker's trajectory is independent of the schedule).
+ * Candidates whose LDS does not fit are skipped.  *chosen (host, may be NULL) receives the waves
+ * per workgroup, negated for an unpaired schedule; muca_get_launch_info gives the full plan. */
 int muca_autotune(muca_ctx *ctx, int64_t probe_sweeps, int32_t *chosen);
+
+/* Current launch plan of the sweep kernels (host struct, filled in). */
+int muca_get_launch_info(muca_ctx *ctx, muca_launch_info *out);
 
 /*
  * Energy and its gradients for stored configurations of system sys (differentiation of

@@ -38,7 +38,7 @@ class Muca:
                  walkers_per_system: int, k_lj_intra=4.0, k_lj_inter=4.0, k_bend=0.25,
                  k_tors=0.0, box_kind=0, box_len=0.0, bin_width=0.05, seed=1702,
                  precision=PREC_FP64, resync_sweeps=0, drift_tol=0.0, crank_max=np.pi / 3,
-                 cap_rho=0.8, trans_max=0.3, rigid_per_sweep=0, waves_per_block=0,
+                 cap_rho=0.8, trans_max=0.3, rigid_per_sweep=0, waves_per_block=0, walkers_per_wave=0,
                  stream: Optional[int] = None):
         L = load()
         self._keep = dict(
@@ -64,7 +64,7 @@ class Muca:
             float(box_len), _ptr(k["elo"], C.c_double), _ptr(k["nb"], C.c_int32),
             float(bin_width), self.walkers, int(seed), int(precision), int(resync_sweeps),
             float(drift_tol), float(crank_max), float(cap_rho), float(trans_max),
-            int(rigid_per_sweep), int(waves_per_block), stream)
+            int(rigid_per_sweep), int(waves_per_block), int(walkers_per_wave), stream)
         h = C.c_void_p()
         check(L.muca_init(C.byref(cfg), C.byref(h)))
         self._h = h
@@ -198,6 +198,13 @@ class Muca:
         ch = C.c_int32(0)
         self._ck(self._L.muca_autotune(self._h, int(probe_sweeps), C.byref(ch)))
         return ch.value
+
+    def launch_info(self) -> dict:
+        """Current sweep launch plan (walkers per wave, waves per block, pairing, workgroups,
+        LDS bytes, sweeps per launch)."""
+        li = _lib.LaunchInfo()
+        self._ck(self._L.muca_get_launch_info(self._h, C.byref(li)))
+        return {f: getattr(li, f) for f, _ in li._fields_}
 
     # ---- differentiation (device pointers, e.g. torch tensors' data_ptr()) ----
     def energy_fwd_ptr(self, sys: int, x_ptr: int, n_cfg: int, theta, e_ptr: int):

@@ -24,7 +24,8 @@ class MucaConfig(C.Structure):
                 ("seed", C.c_uint64), ("precision", C.c_int32), ("resync_sweeps", C.c_int32),
                 ("drift_tol", C.c_double), ("crank_max", C.c_double), ("cap_rho", C.c_double),
                 ("trans_max", C.c_double), ("rigid_per_sweep", C.c_int32),
-                ("waves_per_block", C.c_int32), ("stream", C.c_void_p)]
+                ("waves_per_block", C.c_int32), ("walkers_per_wave", C.c_int32),
+                ("stream", C.c_void_p)]
 
 
 class IterStats(C.Structure):
@@ -36,6 +37,12 @@ class WalkerCounters(C.Structure):
     _fields_ = [("moves", C.c_uint64), ("accepted", C.c_uint64), ("rigid_moves", C.c_uint64),
                 ("rigid_accepted", C.c_uint64), ("window_rejects", C.c_uint64),
                 ("sweeps", C.c_uint64), ("max_drift", C.c_double)]
+
+
+class LaunchInfo(C.Structure):
+    _fields_ = [("walkers_per_wave", C.c_int32), ("waves_per_block", C.c_int32),
+                ("paired", C.c_int32), ("workgroups", C.c_int32), ("lds_bytes", C.c_int64),
+                ("sweeps_per_launch", C.c_int64)]
 
 
 class AnalysisIn(C.Structure):
@@ -62,6 +69,7 @@ EXPORTS = ["muca_init", "muca_sweep", "muca_update_weights", "muca_iterate",
            "muca_get_stats_history", "muca_synchronize", "muca_get_histogram",
            "muca_get_weights", "muca_set_weights", "muca_get_walkers", "muca_set_walkers",
            "muca_set_accept_log", "muca_get_accept_log", "muca_get_state", "muca_set_state",
+           "muca_get_launch_info",
            "muca_autotune", "muca_energy_fwd", "muca_energy_bwd",
            "muca_reweight_workspace_bytes", "muca_reweight_fwd", "muca_reweight_bwd",
            "microcanonical_analyze", "muca_last_error", "muca_destroy"]

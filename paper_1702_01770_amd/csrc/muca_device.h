@@ -132,6 +132,24 @@ __device__ __forceinline__ double wave_sum_d(double v) {
     return (rl_d(v, 0) + rl_d(v, 16)) + (rl_d(v, 32) + rl_d(v, 48));
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
+                                                                 0xf, 0xf, false));
+}
+
+// FP32 sum over the 64 lanes (same butterfly as wave_sum_d), returned in FP64, result uniform.
+__device__ __forceinline__ double wave_sum_f(float v) {
+    v += dpp_f<0xB1>(v);
+    v += dpp_f<0x4E>(v);
+    v += dpp_f<0x141>(v);
+    v += dpp_f<0x140>(v);
+    return (double)((rl_f(v, 0) + rl_f(v, 16)) + (rl_f(v, 32) + rl_f(v, 48)));
+}
+
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_d(v); }
+__device__ __forceinline__ double wave_sum(float v) { return wave_sum_f(v); }
+
 __device__ __forceinline__ int wave_min_i(int v) {
     for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
     return v;

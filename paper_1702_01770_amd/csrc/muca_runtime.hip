@@ -56,6 +56,9 @@ struct muca_ctx {
     IterStatsDev *d_stats = nullptr;
     int stats_cap = 4096;
     int wpb = 16, n_items = 0;
+    int pack = 1;              // walkers per wave: 1 (k_sweep) or 2 (k_sweep_pair)
+    int pos_stride = 0;        // LDS coordinate stride of k_sweep_pair
+    int pair_slots = 1;        // bead slots per lane of k_sweep_pair (32 lanes per walker)
     bool paired = true;
     size_t lds_limit = 0;
     size_t lds_bytes = 0;
@@ -114,13 +117,18 @@ static size_t lds_for_bins(long long bins) {
            sizeof(double) * kMaxTypes * kMaxTypes;
 }
 
-// Workgroup schedule.  A workgroup runs wpb walkers, one per wave; waves w, w+4, w+8, w+12
-// share SIMD w % 4.  The cost of a walker is proportional to its chain length (trial moves per
+// LDS of one workgroup holding n_sys systems with `bins` bins in total.
+static size_t lds_need(const muca_ctx *ctx, long long bins, int n_sys, int wpb, int pack) {
+    return pack == 2 ? sweep_pair_lds_bytes(bins, n_sys, wpb, ctx->pos_stride) : lds_for_bins(bins);
+}
+
+// Workgroup schedule.  A workgroup runs wpb waves of `pack` walkers each (consecutive walkers of
+// one system share a wave when pack = 2); waves w, w+4, w+8, w+12 share SIMD w % 4.  The cost of a walker is proportional to its chain length (trial moves per
 // sweep), so when several systems are sampled, the longest remaining system is paired with the
 // shortest one whose LDS tables fit beside it, and their walkers are interleaved so that every
 // SIMD gets half of each: long and short chains then finish together.  Workgroups of the
 // longest chains are listed first.
-static int build_schedule(muca_ctx *ctx, int wpb, bool pair) {
+static int build_schedule(muca_ctx *ctx, int wpb, bool pair, int pack) {
     const int dev_lds = (int)ctx->lds_limit;
     std::vector<WorkItem> items;
     std::vector<int> order(ctx->n_sys);
@@ -140,17 +148,20 @@ static int build_schedule(muca_ctx *ctx, int wpb, bool pair) {
     while (lo <= hi) {
         const int A = order[lo], B = order[hi];
         const bool can_pair = pair && wpb >= 8 && lo < hi &&
-            lds_for_bins((long long)ctx->sys[A].n_bins + ctx->sys[B].n_bins) <= (size_t)dev_lds;
+            lds_need(ctx, (long long)ctx->sys[A].n_bins + ctx->sys[B].n_bins, 2, wpb, pack) <=
+                (size_t)dev_lds;
         if (!can_pair) {
             // single-system workgroups for the rest of A
             while (next[A] < ctx->W) {
                 WorkItem w = blank();
                 w.n_sys = 1; w.sys[0] = A; w.lds_off[0] = 0;
-                for (int v = 0; v < wpb && next[A] < ctx->W; ++v)
-                    w.walker[v] = ctx->sys[A].walker_off + next[A]++;
+                for (int v = 0; v < wpb && next[A] < ctx->W; ++v) {
+                    w.walker[v] = ctx->sys[A].walker_off + next[A];
+                    next[A] += pack;
+                }
                 items.push_back(w);
             }
-            lds_max = std::max(lds_max, lds_for_bins(ctx->sys[A].n_bins));
+            lds_max = std::max(lds_max, lds_need(ctx, ctx->sys[A].n_bins, 1, wpb, pack));
             ++lo;
             continue;
         }
@@ -165,17 +176,23 @@ static int build_schedule(muca_ctx *ctx, int wpb, bool pair) {
             for (int v = 0; v < wpb; ++v) {
                 const bool use_a = ((v / 4) % 2) == 0;
                 if (use_a && na < half && next[A] < ctx->W) {
-                    w.walker[v] = ctx->sys[A].walker_off + next[A]++; w.slot[v] = 0; ++na;
+                    w.walker[v] = ctx->sys[A].walker_off + next[A]; w.slot[v] = 0; ++na;
+                    next[A] += pack;
                 } else if (!use_a && nb < half && next[B] < ctx->W) {
-                    w.walker[v] = ctx->sys[B].walker_off + next[B]++; w.slot[v] = 1; ++nb;
+                    w.walker[v] = ctx->sys[B].walker_off + next[B]; w.slot[v] = 1; ++nb;
+                    next[B] += pack;
                 }
             }
             items.push_back(w);
         }
-        lds_max = std::max(lds_max, lds_for_bins((long long)ctx->sys[A].n_bins + ctx->sys[B].n_bins));
+        lds_max = std::max(lds_max, lds_need(ctx, (long long)ctx->sys[A].n_bins + ctx->sys[B].n_bins,
+                                             2, wpb, pack));
         if (next[A] >= ctx->W) ++lo;
         if (next[B] >= ctx->W) --hi;
     }
+    if (lds_max > (size_t)dev_lds)
+        return fail(ctx, MUCA_E_INVAL, "workgroup schedule needs " + std::to_string(lds_max) +
+                                           " bytes of LDS (device limit " + std::to_string(dev_lds) + ")");
     if (ctx->d_work) (void)hipFree(ctx->d_work);
     ctx->d_work = nullptr;
     CK(hipMalloc(&ctx->d_work, sizeof(WorkItem) * items.size()));
@@ -183,6 +200,7 @@ static int build_schedule(muca_ctx *ctx, int wpb, bool pair) {
     ctx->n_items = (int)items.size();
     ctx->wpb = wpb;
     ctx->paired = pair;
+    ctx->pack = pack;
     ctx->lds_bytes = lds_max;
     ctx->args.work = ctx->d_work;
     drop_graphs(ctx);
@@ -193,8 +211,12 @@ static int launch_chunked(muca_ctx *ctx, long long n_sweeps) {
     long long left = n_sweeps;
     while (left > 0) {
         const long long c = std::min<long long>(left, ctx->chunk_sweeps);
-        CK(launch_sweep(ctx->args, ctx->fp64, ctx->slots, ctx->periodic, ctx->n_items, ctx->wpb,
-                        ctx->lds_bytes, c, ctx->stream));
+        if (ctx->pack == 2)
+            CK(launch_sweep_pair(ctx->args, ctx->fp64, ctx->pair_slots, ctx->periodic, ctx->n_items,
+                                 ctx->wpb, ctx->lds_bytes, c, ctx->pos_stride, ctx->stream));
+        else
+            CK(launch_sweep(ctx->args, ctx->fp64, ctx->slots, ctx->periodic, ctx->n_items, ctx->wpb,
+                            ctx->lds_bytes, c, ctx->stream));
         left -= c;
     }
     return MUCA_OK;
@@ -281,6 +303,9 @@ static int validate(const muca_config *c, std::string &why) {
     if (c->precision != MUCA_PREC_FP64 && c->precision != MUCA_PREC_FP32_SPLIT) { why = "bad precision"; return MUCA_E_INVAL; }
     if (c->resync_sweeps < 0 || c->rigid_per_sweep < 0) { why = "negative resync/rigid count"; return MUCA_E_INVAL; }
     if (c->waves_per_block < 0 || c->waves_per_block > 16) { why = "waves_per_block must be 0..16"; return MUCA_E_INVAL; }
+    if (c->walkers_per_wave < 0 || c->walkers_per_wave > 2) { why = "walkers_per_wave must be 0, 1 or 2"; return MUCA_E_INVAL; }
+    if (c->walkers_per_wave == 2 && (c->walkers_per_system % 2) != 0) { why = "walkers_per_wave = 2 needs an even walkers_per_system"; return MUCA_E_INVAL; }
+    if (c->walkers_per_wave == 2 && c->waves_per_block > 8) { why = "walkers_per_wave = 2 allows at most 8 waves per block"; return MUCA_E_INVAL; }
     return MUCA_OK;
 }
 
@@ -346,6 +371,8 @@ int muca_init(const muca_config *cfg, muca_ctx **out) {
     ctx->total_bins = bin_off;
     ctx->slots = ctx->max_beads > 64 ? 2 : 1;
     ctx->npad = 64 * ctx->slots;
+    ctx->pair_slots = (ctx->max_beads + 31) / 32;
+    ctx->pos_stride = (ctx->max_beads + 1) & ~1;
     ctx->lds_bytes = (size_t)ctx->max_bins * (sizeof(double) * 2 + sizeof(unsigned int)) +
                      sizeof(double) * kMaxTypes * kMaxTypes;
     int dev_lds = 0;
@@ -495,12 +522,20 @@ int muca_init(const muca_config *cfg, muca_ctx **out) {
     rc = sync_and_check(ctx);
     if (rc != MUCA_OK) return bail(rc);
 
-    int wpb = cfg->waves_per_block > 0 ? cfg->waves_per_block : 16;
-    wpb = std::min(wpb, ctx->W);
     // keep single launches short: about 2e5 trial moves per walker
     ctx->chunk_sweeps = std::max(1, 200000 / std::max(1, ctx->max_beads));
     ctx->lds_limit = (size_t)dev_lds;
-    rc = build_schedule(ctx, wpb, true);
+    // default: two walkers per wave when the walkers pair up, 8 such waves per workgroup
+    int pack = cfg->walkers_per_wave > 0 ? cfg->walkers_per_wave : (ctx->W % 2 == 0 ? 2 : 1);
+    if (cfg->walkers_per_wave == 0 && cfg->waves_per_block > 8) pack = 1;
+    int wpb = cfg->waves_per_block > 0 ? cfg->waves_per_block : (pack == 2 ? 8 : 16);
+    wpb = std::max(1, std::min(wpb, ctx->W / pack));
+    rc = build_schedule(ctx, wpb, true, pack);
+    if (rc != MUCA_OK && cfg->walkers_per_wave == 0 && pack == 2) {
+        pack = 1;      // the coordinate mirror does not fit beside the tables: one walker per wave
+        wpb = std::min(cfg->waves_per_block > 0 ? cfg->waves_per_block : 16, ctx->W);
+        rc = build_schedule(ctx, wpb, true, pack);
+    }
     if (rc != MUCA_OK) return bail(rc);
     *out = ctx;
     return MUCA_OK;
@@ -852,6 +887,17 @@ int muca_energy_bwd(muca_ctx *ctx, int32_t sys, const float *x, int64_t n_cfg,
     return MUCA_OK;
 }
 
+int muca_get_launch_info(muca_ctx *ctx, muca_launch_info *out) {
+    if (!ctx || !out) return fail(ctx, MUCA_E_INVAL, "null argument");
+    out->walkers_per_wave = ctx->pack;
+    out->waves_per_block = ctx->wpb;
+    out->paired = ctx->paired ? 1 : 0;
+    out->workgroups = ctx->n_items;
+    out->lds_bytes = (int64_t)ctx->lds_bytes;
+    out->sweeps_per_launch = ctx->chunk_sweeps;
+    return MUCA_OK;
+}
+
 int muca_autotune(muca_ctx *ctx, int64_t probe_sweeps, int32_t *chosen) {
     if (!ctx) return fail(nullptr, MUCA_E_INVAL, "null context");
     if (probe_sweeps < 1) return fail(ctx, MUCA_E_INVAL, "probe_sweeps < 1");
@@ -861,19 +907,26 @@ int muca_autotune(muca_ctx *ctx, int64_t probe_sweeps, int32_t *chosen) {
     std::vector<char> saved(bytes);
     rc = muca_get_state(ctx, saved.data(), &bytes);
     if (rc != MUCA_OK) return rc;
-    const int cands[] = {16, 8, 4, 2, 1};
-    int best = ctx->wpb;
-    bool best_pair = ctx->paired;
+    struct Cand { int pack, wpb; bool pair; };
+    std::vector<Cand> cands;
+    for (int pack = 2; pack >= 1; --pack) {
+        if (pack == 2 && ctx->W % 2 != 0) continue;
+        for (int pr = 1; pr >= 0; --pr)
+            for (int c : {16, 8, 4, 2, 1}) {
+                if (pack == 2 && c > 8) continue;
+                if (c * pack > ctx->W) continue;
+                if (!pr && (ctx->n_sys == 1 || c < 8)) continue;   // pairing makes no difference
+                cands.push_back(Cand{pack, c, pr != 0});
+            }
+    }
+    Cand best{ctx->pack, ctx->wpb, ctx->paired};
     float best_ms = 1e30f;
     hipEvent_t e0, e1;
     CK(hipEventCreate(&e0));
     CK(hipEventCreate(&e1));
-    for (int ci = 0; ci < 10; ++ci) {
-        const int c = cands[ci % 5];
-        const bool pr = ci < 5;
-        if (c > ctx->W) continue;
-        if (!pr && (ctx->n_sys == 1 || c < 8)) continue;   // pairing makes no difference
-        rc = build_schedule(ctx, c, pr);
+    for (const Cand &cd : cands) {
+        rc = build_schedule(ctx, cd.wpb, cd.pair, cd.pack);
+        if (rc == MUCA_E_INVAL) { rc = MUCA_OK; continue; }   // does not fit in LDS
         if (rc != MUCA_OK) break;
         rc = launch_chunked(ctx, 1);                 // warm the code path
         if (rc != MUCA_OK) break;
@@ -884,7 +937,7 @@ int muca_autotune(muca_ctx *ctx, int64_t probe_sweeps, int32_t *chosen) {
         CK(hipEventSynchronize(e1));
         float ms = 0.f;
         CK(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best_ms) { best_ms = ms; best = c; best_pair = pr; }
+        if (ms < best_ms) { best_ms = ms; best = cd; }
         rc = muca_set_state(ctx, saved.data(), bytes);
         if (rc != MUCA_OK) break;
     }
@@ -893,9 +946,10 @@ int muca_autotune(muca_ctx *ctx, int64_t probe_sweeps, int32_t *chosen) {
     if (rc != MUCA_OK) return rc;
     rc = sync_and_check(ctx);
     if (rc != MUCA_OK) return rc;
-    rc = build_schedule(ctx, best, best_pair);
+    rc = build_schedule(ctx, best.wpb, best.pair, best.pack);
     if (rc != MUCA_OK) return rc;
-    if (chosen) *chosen = best_pair ? best : -best;
+    ctx->err.clear();
+    if (chosen) *chosen = best.pair ? best.wpb : -best.wpb;
     return MUCA_OK;
 }
 

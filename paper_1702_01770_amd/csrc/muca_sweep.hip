@@ -64,9 +64,14 @@ __device__ __forceinline__ double pair_energy(double dx, double dy, double dz, d
     }
 }
 
+// Accumulator of a move's Delta E: FP64 in FP64 mode; FP32 in the FP32-split mode (pair terms
+// are FP32 there, and the running energy they are added to stays FP64).
 template <bool FP64>
-__device__ __forceinline__ double pair_delta(double dxo, double dyo, double dzo, double dxn,
-                                             double dyn, double dzn, double k, double kc) {
+using AccT = typename std::conditional<FP64, double, float>::type;
+
+template <bool FP64>
+__device__ __forceinline__ AccT<FP64> pair_delta(double dxo, double dyo, double dzo, double dxn,
+                                                 double dyn, double dzn, double k, double kc) {
     if constexpr (FP64) {
         return pair_energy<true>(dxn, dyn, dzn, k, kc) - pair_energy<true>(dxo, dyo, dzo, k, kc);
     } else {
@@ -78,7 +83,7 @@ __device__ __forceinline__ double pair_delta(double dxo, double dyo, double dzo,
         float s3o = so * so * so, s3n = sn * sn * sn;
         float kf = (float)k, kcf = (float)kc;
         float eo = s3o * (kf * s3o - kcf), en = s3n * (kf * s3n - kcf);
-        return (double)(en - eo);
+        return en - eo;
     }
 }
 
@@ -224,7 +229,7 @@ __device__ void run_walker(const SweepArgs &a, const SysDev &sd, int sys, int w,
             const bool fst = bi_first(infb), lst = bi_last(infb);
             const double xbx = bc_d(px, b), xby = bc_d(py, b), xbz = bc_d(pz, b);
             double nx, ny, nz;
-            double acc = 0.0;
+            AccT<FP64> acc = 0;
             if (fst || lst) {
                 const int an = fst ? b + 1 : b - 1;
                 const double xax = bc_d(px, an), xay = bc_d(py, an), xaz = bc_d(pz, an);
@@ -247,10 +252,8 @@ __device__ void run_walker(const SweepArgs &a, const SysDev &sd, int sys, int w,
                 nx = xpx + (vx * c + cx * sn + kx * kv * omc);
                 ny = xpy + (vy * c + cy * sn + ky * kv * omc);
                 nz = xpz + (vz * c + cz * sn + kz * kv * omc);
-                // the bend at the moved bead itself: both of its bonds change
-                const double co = vx * (xnx - xbx) + vy * (xny - xby) + vz * (xnz - xbz);
-                const double cn = (nx - xpx) * (xnx - nx) + (ny - xpy) * (xny - ny) + (nz - xpz) * (xnz - nz);
-                if (lane == 0) acc = a.k_bend * (co - cn);
+                // The bend at the moved bead itself is unchanged: its bonds are v and a - v, and a
+                // rotation about a keeps both |v| and v.a, hence v.(a - v).
             }
             // bond b-1 changes by -(x'_b - x_b), bond b by +(x'_b - x_b): every other bending or
             // torsion term that uses one of them changes by a multiple of u_j . (x'_b - x_b)
@@ -284,11 +287,11 @@ __device__ void run_walker(const SweepArgs &a, const SysDev &sd, int sys, int w,
                         if (j == b + 1) coef = c_p1;
                         if (j == b - 3) coef = -ktors;
                         if (j == b + 2) coef = ktors;
-                        acc += coef * (ux[s] * mx + uy[s] * my + uz[s] * mz);
+                        acc += (AccT<FP64>)(coef * (ux[s] * mx + uy[s] * my + uz[s] * mz));
                     }
                 }
             }
-            const double dE = wave_sum_d(acc);
+            const double dE = wave_sum(acc);
             const double En = E + dE;
             const double t = (En - e_lo) * a.inv_bin;
             const bool inwin = (t >= 0.0) && (t < (double)K);
@@ -308,10 +311,10 @@ __device__ void run_walker(const SweepArgs &a, const SysDev &sd, int sys, int w,
                     if (j == b - 1 && !fst) { ux[s] = nx - px[s]; uy[s] = ny - py[s]; uz[s] = nz - pz[s]; }
                 }
                 if (!lst) {
-                    const double x1 = bc_d(px, b + 1), y1 = bc_d(py, b + 1), z1 = bc_d(pz, b + 1);
+                    // bond b becomes x_{b+1} - x'_b = (x_{b+1} - x_b) - (x'_b - x_b)
 #pragma unroll
                     for (int s = 0; s < SLOTS; ++s)
-                        if (lane + 64 * s == b) { ux[s] = x1 - nx; uy[s] = y1 - ny; uz[s] = z1 - nz; }
+                        if (lane + 64 * s == b) { ux[s] -= mx; uy[s] -= my; uz[s] -= mz; }
                 }
 #pragma unroll
                 for (int s = 0; s < SLOTS; ++s)
@@ -338,7 +341,7 @@ __device__ void run_walker(const SweepArgs &a, const SysDev &sd, int sys, int w,
                         const double tz = a.trans_max * (2.0 * u01(r1.w) - 1.0);
                         const double lnu_r = log(u01(r2.x));
                         const int cs = sd.chain_start[ch], ce = sd.chain_start[ch + 1];
-                        double racc = 0.0;
+                        AccT<FP64> racc = 0;
                         for (int ib = cs; ib < ce; ++ib) {
                             const double xi = bc_d(px, ib), yi = bc_d(py, ib), zi = bc_d(pz, ib);
                             const double xs = xi + tx, ys = yi + ty, zs = zi + tz;
@@ -362,7 +365,7 @@ __device__ void run_walker(const SweepArgs &a, const SysDev &sd, int sys, int w,
                                 }
                             }
                         }
-                        const double rdE = wave_sum_d(racc);
+                        const double rdE = wave_sum(racc);
                         const double rEn = E + rdE;
                         const double rt = (rEn - e_lo) * a.inv_bin;
                         const bool rin = (rt >= 0.0) && (rt < (double)K);

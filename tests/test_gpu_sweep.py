@@ -37,8 +37,13 @@ def _oracle_walkers(orc, wl, sys_index, walkers, n_sweeps, weights=None, log_mov
     return H, out
 
 
-def _compare(lib, orc, wl, walkers, n_sweeps, weights_by_sys=None, log_moves=None):
-    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=walkers, precision=0)
+def _compare(lib, orc, wl, walkers, n_sweeps, weights_by_sys=None, log_moves=None, pack=1,
+             **over):
+    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=walkers, precision=0,
+                               walkers_per_wave=pack, **over)
+    info = m.launch_info()
+    assert info["walkers_per_wave"] == pack
+    print("launch plan", info)
     if weights_by_sys:
         for s, Wt in weights_by_sys.items():
             m.set_weights(s, Wt.beta, Wt.alpha, Wt.g)
@@ -68,30 +73,45 @@ def _compare(lib, orc, wl, walkers, n_sweeps, weights_by_sys=None, log_moves=Non
     m.close()
 
 
-def test_fp64_single_chain_flat_weights(lib, orc):
+# pack = walkers per wavefront: 1 runs k_sweep, 2 runs k_sweep_pair (two 32-lane halves)
+@pytest.mark.parametrize("pack", [1, 2])
+def test_fp64_single_chain_flat_weights(lib, orc, pack):
     wl = workloads.single_chain()
-    _compare(lib, orc, wl, walkers=1, n_sweeps=3000)
+    _compare(lib, orc, wl, walkers=pack, n_sweeps=3000, pack=pack)
 
 
-def test_fp64_single_chain_muca_weights_several_walkers(lib, orc):
+@pytest.mark.parametrize("pack", [1, 2])
+def test_fp64_single_chain_muca_weights_several_walkers(lib, orc, pack):
     wl = workloads.single_chain()
     res = orc.muca(wl, n_iter=4, n_sweeps=4000, walkers=2)
-    _compare(lib, orc, wl, walkers=6, n_sweeps=1500, weights_by_sys={0: res["weights"]})
+    _compare(lib, orc, wl, walkers=6, n_sweeps=1500, weights_by_sys={0: res["weights"]},
+             pack=pack)
 
 
-def test_fp64_batched_uneven_lengths(lib, orc):
+@pytest.mark.parametrize("pack", [1, 2])
+def test_fp64_batched_uneven_lengths(lib, orc, pack):
     wl = workloads.batched_chains(n_seq=3, n_min=13, n_max=60)
-    _compare(lib, orc, wl, walkers=3, n_sweeps=300)
+    _compare(lib, orc, wl, walkers=2 + pack, n_sweeps=300, pack=pack)
 
 
-def test_fp64_aggregation_periodic_rigid(lib, orc):
+@pytest.mark.parametrize("pack", [1, 2])
+def test_fp64_batched_paired_workgroups(lib, orc, pack):
+    """Long and short systems sharing workgroups (8 waves: half run the longest remaining
+    system, half the shortest), with a ragged last workgroup per system."""
+    wl = workloads.batched_chains(n_seq=3, n_min=13, n_max=60)
+    _compare(lib, orc, wl, walkers=18, n_sweeps=60, pack=pack, waves_per_block=8)
+
+
+@pytest.mark.parametrize("pack", [1, 2])
+def test_fp64_aggregation_periodic_rigid(lib, orc, pack):
     wl = workloads.aggregation()
-    _compare(lib, orc, wl, walkers=3, n_sweeps=400)
+    _compare(lib, orc, wl, walkers=2 + pack, n_sweeps=400, pack=pack)
 
 
-def test_fp64_cross_seeding_two_slots_torsion(lib, orc):
+@pytest.mark.parametrize("pack", [1, 2])
+def test_fp64_cross_seeding_two_slots_torsion(lib, orc, pack):
     wl = workloads.cross_seeding()
-    _compare(lib, orc, wl, walkers=2, n_sweeps=200)
+    _compare(lib, orc, wl, walkers=2, n_sweeps=200, pack=pack)
 
 
 def test_weight_update_matches_oracle(lib, orc):
@@ -163,3 +183,56 @@ def test_window_error_is_reported(lib):
     with pytest.raises(lib.MucaError) as ei:
         lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=1)
     assert "WINDOW" in str(ei.value)
+
+
+def test_checkpoint_resume_is_bit_identical(lib):
+    """Stopping after n sweeps, saving the state and resuming in a fresh context gives exactly
+    the trajectory, histogram and weights of an uninterrupted run (counter-based streams carry no
+    generator state)."""
+    wl = workloads.aggregation(walkers=8)
+    p0 = workloads.initial_positions(wl)
+    a = lib.Muca.from_workload(wl, p0, precision=1, resync_sweeps=50)
+    a.sweep(150)
+    a.update_weights()
+    a.sweep(100)
+    pa, ea, ca = a.walkers_state(0)
+    ha = a.histogram(0)
+    wa = a.weights(0)
+    b = lib.Muca.from_workload(wl, p0, precision=1, resync_sweeps=50)
+    b.sweep(150)
+    b.update_weights()
+    blob = b.get_state()
+    b.close()
+    c = lib.Muca.from_workload(wl, p0, precision=1, resync_sweeps=50)
+    c.set_state(blob)
+    c.sweep(100)
+    pc, ec, cc = c.walkers_state(0)
+    assert np.array_equal(pa, pc) and np.array_equal(ea, ec)
+    assert np.array_equal(ha, c.histogram(0))
+    for x, y in zip(wa, c.weights(0)):
+        assert np.array_equal(x, y)
+    for k in ca:
+        assert np.array_equal(ca[k], cc[k])
+    a.close()
+    c.close()
+
+
+def test_drift_detector_fires_on_corrupted_energy(lib):
+    """The FP64 resync compares the running energy with a full recomputation and reports
+    MUCA_E_DRIFT when they differ by more than drift_tol (here a corrupted running energy)."""
+    import struct
+    wl = workloads.aggregation(walkers=4)
+    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), precision=1,
+                               resync_sweeps=10, drift_tol=1e-3)
+    m.sweep(10)
+    blob = bytearray(m.get_state())
+    hdr = struct.unpack_from("6Q", blob, 0)
+    e_off = 48 + 8 * hdr[2]                               # header, then coordinates
+    e0 = struct.unpack_from("d", blob, e_off)[0]
+    struct.pack_into("d", blob, e_off, e0 + 0.01)         # walker 0's running energy is off
+    m.set_state(bytes(blob))
+    m.sweep(10)
+    with pytest.raises(lib.MucaError) as ei:
+        m.synchronize()
+    assert "DRIFT" in str(ei.value)
+    m.close()
