@@ -51,7 +51,7 @@ def make_stream():
     return s
 
 
-def run_gpu(wl, walkers, n_sweeps, steps, warmup, stream, autotune=True):
+def run_gpu(wl, walkers, n_sweeps, steps, warmup, stream, autotune=True, **launch):
     """Run `warmup` then `steps` MUCA iterations; time the steps with HIP events recorded on the
     stream the library launches on."""
     import torch
@@ -59,8 +59,9 @@ def run_gpu(wl, walkers, n_sweeps, steps, warmup, stream, autotune=True):
     import paper_1702_01770_amd as P
     import workloads
     m = P.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=walkers,
-                             stream=stream.cuda_stream)
+                             stream=stream.cuda_stream, **launch)
     chosen = m.autotune(probe_sweeps=max(5, n_sweeps // 200)) if autotune else None
+    plan = m.launch_info()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     if warmup:
@@ -80,7 +81,9 @@ def run_gpu(wl, walkers, n_sweeps, steps, warmup, stream, autotune=True):
         moves += walkers * n_sweeps * sp.n_beads * steps
     _, _, cnt = m.walkers_state(0)
     m.close()
-    return dict(moves=moves, event_ms=ms, wall_s=wall, stats=stats, chosen=chosen,
+    launches = steps * -(-n_sweeps // plan["sweeps_per_launch"])
+    return dict(moves=moves, event_ms=ms, wall_s=wall, stats=stats, chosen=chosen, plan=plan,
+                launches=launches,
                 acc_rate=float(np.sum(cnt["accepted"]) / max(1, np.sum(cnt["moves"]))))
 
 
@@ -107,7 +110,7 @@ def matched_error(stream):
         wl.systems = [sp] * reps                       # 4 independent replicas at once
         m = P.Muca.from_workload(wl, workloads.initial_positions(workloads.single_chain(n=6)) * reps,
                                  walkers=walkers, precision=1, seed=77_000_003,
-                                 stream=stream.cuda_stream)
+                                 resync_sweeps=100, stream=stream.cuda_stream)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         bs = [[] for _ in range(reps)]
@@ -212,6 +215,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-matched", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the launch plan given by --walkers-per-wave / --waves-per-block")
+    ap.add_argument("--walkers-per-wave", type=int, default=0)
+    ap.add_argument("--waves-per-block", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -222,7 +229,9 @@ def main():
     st = make_stream()
     if args.calibrate_copy:
         copy_calibration()
-    r = run_gpu(wl, wl.walkers_per_system, args.sweeps, args.steps, args.warmup, st)
+    r = run_gpu(wl, wl.walkers_per_system, args.sweeps, args.steps, args.warmup, st,
+                autotune=not args.no_autotune, walkers_per_wave=args.walkers_per_wave,
+                waves_per_block=args.waves_per_block)
     sec = r["event_ms"] / 1e3
     value = r["moves"] / sec
     flops_per_step = sum(wl.walkers_per_system * args.sweeps * sp.n_beads *
@@ -236,11 +245,14 @@ def main():
         "dtype": "f32 pair terms + f64 energy/weights", "data": "synthetic",
         "config": {"workload": "batched single chains: 32 seeded A/B sequences, N uniform in "
                                "13..55, 4096 walkers (128/system), FP32-split",
-                   "sweeps_per_step": args.sweeps, "waves_per_block": r["chosen"],
-                   "parallelism": "single GPU"},
+                   "sweeps_per_step": args.sweeps, "parallelism": "single GPU",
+                   "launch_plan": r["plan"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": sweep_traffic()},
+        "sweep_launch": {"launches": r["launches"],
+                         "avg_ms": r["event_ms"] / r["launches"],
+                         "algorithmic_flop_per_launch": flops_per_step * args.steps / r["launches"]},
         "acceptance": r["acc_rate"],
         "wall_s": r["wall_s"],
     }

@@ -50,33 +50,35 @@ __device__ __forceinline__ AccP<FP64> pair_d(double dxo, double dyo, double dzo,
     }
 }
 
-// value of lane (half * 32 + i) for the half this lane belongs to
-__device__ __forceinline__ int hsel_i(int v, int i, bool hi) {
-    const int a = rl_i(v, i), b = rl_i(v, 32 + i);
-    return hi ? b : a;
+// Sum over the 32 lanes of each half, returned to every lane of that half: DPP butterfly to
+// the sum of each 16-lane row, then gfx950's row swap (rows 0<->1, 2<->3) adds the partner row.
+__device__ __forceinline__ double row_pair_sum(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
+    const auto sl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto sh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    const double a = __builtin_bit_cast(double, ((unsigned long long)sh[0] << 32) | sl[0]);
+    const double b = __builtin_bit_cast(double, ((unsigned long long)sh[1] << 32) | sl[1]);
+    return a + b;
 }
-__device__ __forceinline__ double hsel_d(double v, int i, bool hi) {
-    const double a = rl_d(v, i), b = rl_d(v, 32 + i);
-    return hi ? b : a;
-}
-
-// sum over the 32 lanes of each half, returned to every lane of that half
-__device__ __forceinline__ double half_sum(double v, bool hi) {
+__device__ __forceinline__ double half_sum_d(double v) {
     v += dpp_d<0xB1>(v);
     v += dpp_d<0x4E>(v);
     v += dpp_d<0x141>(v);
     v += dpp_d<0x140>(v);
-    const double s0 = rl_d(v, 0) + rl_d(v, 16), s1 = rl_d(v, 32) + rl_d(v, 48);
-    return hi ? s1 : s0;
+    return row_pair_sum(v);
 }
-__device__ __forceinline__ double half_sum(float v, bool hi) {
+// FP32 row sums, combined in FP64 (the 64-bit swap pattern above; the compiler folds the two
+// results of a 32-bit swap of one value into one).
+__device__ __forceinline__ double half_sum_f(float v) {
     v += dpp_f<0xB1>(v);
     v += dpp_f<0x4E>(v);
     v += dpp_f<0x141>(v);
     v += dpp_f<0x140>(v);
-    const float s0 = rl_f(v, 0) + rl_f(v, 16), s1 = rl_f(v, 32) + rl_f(v, 48);
-    return (double)(hi ? s1 : s0);
+    return row_pair_sum((double)v);
 }
+__device__ __forceinline__ double half_sum(double v) { return half_sum_d(v); }
+__device__ __forceinline__ double half_sum(float v) { return half_sum_f(v); }
 
 // ln W(E) = -beta_k E + alpha_k in bin k (Eq. 8)
 __device__ __forceinline__ double lnw_at(const double2 *lw, int k, double e) {
@@ -84,19 +86,28 @@ __device__ __forceinline__ double lnw_at(const double2 *lw, int k, double e) {
     return -w.x * e + w.y;
 }
 
+// Per-move values drawn ahead by the lanes of a half (one move per lane) and read back by the
+// whole half: the rotation cosine / sine or the sphere vector, and ln u.
+struct Staged {
+    double q0, q1, q2, lnu;
+};
+
 struct PairLds {
     const double2 *lw;         // (beta_k, alpha_k) of this walker's system
     unsigned long long *hist;  // device histogram of this walker's system
     const int *binfo;          // bead descriptors of this walker's system
     double *x, *y, *z;         // this walker's coordinates
-    const double *ctab;
+    const double *ctab;        // C_LJ[t][u], t, u < kMaxTypes
+    const void *kc;            // {kappa, kappa C_LJ}[intra / inter][t][u] in the accumulator type
+    int *sb;                   // staged bead index of the next kG moves (+1 spare)
+    Staged *sq;                // staged random values of the next kG moves (+1 spare)
 };
 
 // Full FP64 energy of the walker of this half, from the LDS copy of its coordinates.
 template <int SLOTS, bool PERIODIC>
 __device__ double full_energy_pair(const SweepArgs &a, int N, const PairLds &L,
                                    const double (&px)[SLOTS], const double (&py)[SLOTS],
-                                   const double (&pz)[SLOTS], const int (&inf)[SLOTS], bool hi) {
+                                   const double (&pz)[SLOTS], const int (&inf)[SLOTS]) {
     const int gl = threadIdx.x & 31;
     double acc = 0.0;
     for (int i = 0; i < N; ++i) {
@@ -145,21 +156,29 @@ __device__ double full_energy_pair(const SweepArgs &a, int N, const PairLds &L,
             }
         }
     }
-    return half_sum(acc, hi);
+    return half_sum(acc);
 }
 
 template <bool FP64, int SLOTS, bool PERIODIC>
 __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const PairLds &L,
                          long long n_sweeps) {
+    using A = AccP<FP64>;
+    using A2 = typename std::conditional<FP64, double2, float2>::type;
     const int lane = threadIdx.x & 63, gl = lane & 31;
-    const bool hi = lane >= 32;
-    const int N = sd.n_beads, M = sd.n_chains, K = sd.n_bins;
+    // both halves of the wave sample the same system: these are wave-uniform
+    const int N = __builtin_amdgcn_readfirstlane(sd.n_beads);
+    const int M = __builtin_amdgcn_readfirstlane(sd.n_chains);
+    const int K = __builtin_amdgcn_readfirstlane(sd.n_bins);
     const int npad = a.npad;
     double *P = a.pos + (size_t)w * 3 * npad;
     const double inv_eps = a.inv_bin;
+    const A2 *kct = reinterpret_cast<const A2 *>(L.kc);
 
-    double px[SLOTS], py[SLOTS], pz[SLOTS], ux[SLOTS], uy[SLOTS], uz[SLOTS];
-    int inf[SLOTS];
+    // lane state: coordinates (FP64), bond to the next bead of the chain (accumulator type),
+    // descriptor, chain and row offset into the coupling table
+    double px[SLOTS], py[SLOTS], pz[SLOTS];
+    A ux[SLOTS], uy[SLOTS], uz[SLOTS];
+    int inf[SLOTS], chn[SLOTS], trow[SLOTS];
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const int j = gl + kG * s;
@@ -168,10 +187,14 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
         py[s] = alive ? P[npad + j] : 0.0;
         pz[s] = alive ? P[2 * npad + j] : 0.0;
         inf[s] = alive ? L.binfo[j] : bead_info(0, 255, true, true);
+        chn[s] = bi_chain(inf[s]);
+        trow[s] = bi_type(inf[s]) * kMaxTypes;
         if (alive && !bi_last(inf[s])) {
-            ux[s] = P[j + 1] - px[s]; uy[s] = P[npad + j + 1] - py[s]; uz[s] = P[2 * npad + j + 1] - pz[s];
+            ux[s] = (A)(P[j + 1] - px[s]);
+            uy[s] = (A)(P[npad + j + 1] - py[s]);
+            uz[s] = (A)(P[2 * npad + j + 1] - pz[s]);
         } else {
-            ux[s] = uy[s] = uz[s] = 0.0;
+            ux[s] = uy[s] = uz[s] = 0;
         }
     }
 
@@ -199,112 +222,152 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
     unsigned int *alog = a.acc_log ? a.acc_log + (size_t)w * a.acc_log_words : nullptr;
 
     while (done < total) {
-        // ---- each half prepares the next (up to) 32 moves of its walker, one per lane ----
+        // ---- each half draws the next (up to) 32 moves of its walker, one per lane ----
         const int nblk = (int)min((long long)kG, total - done);
-        const int idx = m + gl;
-        const unsigned long long Sl = S + (unsigned long long)(idx / N);
-        const int ml = idx % N;
-        const U4 r = philox4x32_10((unsigned int)ml, (unsigned int)Sl, (unsigned int)(Sl >> 32), 0u, k0, k1);
-        const int blane = (int)(((unsigned long long)r.x * (unsigned long long)N) >> 32);
-        const double u1 = u01(r.y), u2 = u01(r.z), u3 = u01(r.w);
-        // end bead: g uniform on the sphere; interior bead: rotation cosine / sine
-        const int binf_l = L.binfo[blane];
-        double p0, p1, p2;
-        if (bi_first(binf_l) || bi_last(binf_l)) {
-            const double zc = 2.0 * u1 - 1.0;
-            double spsi, cpsi;
-            sincos(2.0 * M_PI * u2, &spsi, &cpsi);
-            const double sxy = sqrt(fmax(0.0, 1.0 - zc * zc));
-            p0 = sxy * cpsi; p1 = sxy * spsi; p2 = zc;
-        } else {
-            sincos(a.crank_max * (2.0 * u1 - 1.0), &p1, &p0);   // p0 = cos, p1 = sin
-            p2 = 0.0;
+        {
+            const int idx = m + gl;
+            const unsigned long long Sl = S + (unsigned long long)(idx / N);
+            const int ml = idx % N;
+            const U4 r = philox4x32_10((unsigned int)ml, (unsigned int)Sl, (unsigned int)(Sl >> 32),
+                                       0u, k0, k1);
+            const int blane = (int)(((unsigned long long)r.x * (unsigned long long)N) >> 32);
+            const double u1 = u01(r.y), u2 = u01(r.z), u3 = u01(r.w);
+            // end bead: g uniform on the sphere; interior bead: rotation cosine / sine
+            const int binf_l = L.binfo[blane];
+            Staged q;
+            if (bi_first(binf_l) || bi_last(binf_l)) {
+                const double zc = 2.0 * u1 - 1.0;
+                double spsi, cpsi;
+                sincos(2.0 * M_PI * u2, &spsi, &cpsi);
+                const double sxy = sqrt(fmax(0.0, 1.0 - zc * zc));
+                q.q0 = sxy * cpsi; q.q1 = sxy * spsi; q.q2 = zc;
+            } else {
+                sincos(a.crank_max * (2.0 * u1 - 1.0), &q.q1, &q.q0);   // q0 = cos, q1 = sin
+                q.q2 = 0.0;
+            }
+            q.lnu = log(u3);
+            L.sb[gl] = blane;
+            L.sq[gl] = q;
+            if (gl == 0) L.sb[kG] = 0;      // spare entry read by the prefetch of the last move
+            __builtin_amdgcn_wave_barrier();
         }
-        const double lnu_l = log(u3);
+        int b_nx = L.sb[0];
+        int inf_nx = L.binfo[b_nx];
+        A2 kk_nx[SLOTS];
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s)
+            kk_nx[s] = kct[(chn[s] == bi_chain(inf_nx) ? 0 : kMaxTypes * kMaxTypes) + trow[s] + bi_type(inf_nx)];
 
         for (int i = 0; i < nblk; ++i) {
-            const int b = hsel_i(blane, i, hi);
-            const int infb = L.binfo[b];
+            const int b = b_nx, infb = inf_nx;
+            A2 kk[SLOTS];
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) kk[s] = kk_nx[s];
+            const Staged q = L.sq[i];
+            b_nx = L.sb[i + 1];                 // prefetch: the draws do not depend on this move
+            inf_nx = L.binfo[b_nx];
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s)
+                kk_nx[s] = kct[(chn[s] == bi_chain(inf_nx) ? 0 : kMaxTypes * kMaxTypes) + trow[s] +
+                               bi_type(inf_nx)];
             const int tb = bi_type(infb), cb = bi_chain(infb);
             const bool fst = bi_first(infb), lst = bi_last(infb);
-            const double q0 = hsel_d(p0, i, hi), q1 = hsel_d(p1, i, hi), q2 = hsel_d(p2, i, hi);
+            const int bm = fst ? b : b - 1, bp = lst ? b : b + 1;
             const double xbx = L.x[b], xby = L.y[b], xbz = L.z[b];
+            const double xmx = L.x[bm], xmy = L.y[bm], xmz = L.z[bm];
+            const double xpx = L.x[bp], xpy = L.y[bp], xpz = L.z[bp];
             double nx, ny, nz;
             if (fst || lst) {
-                const int an = fst ? b + 1 : b - 1;
-                const double xax = L.x[an], xay = L.y[an], xaz = L.z[an];
-                const double vx = (xbx - xax) + a.cap_rho * q0;
-                const double vy = (xby - xay) + a.cap_rho * q1;
-                const double vz = (xbz - xaz) + a.cap_rho * q2;
+                // end bead: new bond along (x_b - x_a) + rho g, unit length, from anchor a
+                const double xax = fst ? xpx : xmx, xay = fst ? xpy : xmy, xaz = fst ? xpz : xmz;
+                const double vx = (xbx - xax) + a.cap_rho * q.q0;
+                const double vy = (xby - xay) + a.cap_rho * q.q1;
+                const double vz = (xbz - xaz) + a.cap_rho * q.q2;
                 const double rv = rsqrt(vx * vx + vy * vy + vz * vz);
                 nx = xax + vx * rv; ny = xay + vy * rv; nz = xaz + vz * rv;
             } else {
-                const double xpx = L.x[b - 1], xpy = L.y[b - 1], xpz = L.z[b - 1];
-                const double xnx = L.x[b + 1], xny = L.y[b + 1], xnz = L.z[b + 1];
-                const double c = q0, sn = q1;
-                const double ax = xnx - xpx, ay = xny - xpy, az = xnz - xpz;
+                // crankshaft: rotate x_b about the axis x_{b-1} -> x_{b+1} (Rodrigues)
+                const double c = q.q0, sn = q.q1;
+                const double ax = xpx - xmx, ay = xpy - xmy, az = xpz - xmz;
                 const double ra = rsqrt(ax * ax + ay * ay + az * az);
                 const double kx = ax * ra, ky = ay * ra, kz = az * ra;
-                const double vx = xbx - xpx, vy = xby - xpy, vz = xbz - xpz;
+                const double vx = xbx - xmx, vy = xby - xmy, vz = xbz - xmz;
                 const double cx = ky * vz - kz * vy, cy = kz * vx - kx * vz, cz = kx * vy - ky * vx;
                 const double kv = kx * vx + ky * vy + kz * vz;
                 const double omc = 1.0 - c;
-                nx = xpx + (vx * c + cx * sn + kx * kv * omc);
-                ny = xpy + (vy * c + cy * sn + ky * kv * omc);
-                nz = xpz + (vz * c + cz * sn + kz * kv * omc);
+                nx = xmx + (vx * c + cx * sn + kx * kv * omc);
+                ny = xmy + (vy * c + cy * sn + ky * kv * omc);
+                nz = xmz + (vz * c + cz * sn + kz * kv * omc);
             }
+            // bond b-1 changes by -m, bond b by +m (m = x'_b - x_b): every other bending or
+            // torsion term that uses one of them changes by a multiple of u_j . m
             const double mx = nx - xbx, my = ny - xby, mz = nz - xbz;
-            const double kbend = a.k_bend, ktors = a.k_tors;
-            const double c_m2 = -kbend + (lst ? 0.0 : ktors);
-            const double c_p1 = kbend - (fst ? 0.0 : ktors);
-            AccP<FP64> acc = 0;
+            const A mxa = (A)mx, mya = (A)my, mza = (A)mz;
+            const A kbend = (A)a.k_bend, ktors = (A)a.k_tors;
+            const A c_m2 = lst ? -kbend : -kbend + ktors;   // j = b-2: bend(b-2), torsion(b-2)
+            const A c_p1 = fst ? kbend : kbend - ktors;     // j = b+1: bend(b), torsion(b-1)
+            A acc = 0;
 #pragma unroll
             for (int s = 0; s < SLOTS; ++s) {
+                if (s > 0 && kG * s >= N) break;         // wave-uniform: no bead in this slot
                 const int j = gl + kG * s;
-                if (j < N && j != b) {
-                    const bool same = bi_chain(inf[s]) == cb;
-                    if (!(same && (j == b - 1 || j == b + 1))) {
-                        double dxo = px[s] - xbx, dyo = py[s] - xby, dzo = pz[s] - xbz;
-                        double dxn = px[s] - nx, dyn = py[s] - ny, dzn = pz[s] - nz;
-                        if constexpr (PERIODIC) {
-                            dxo = min_img(dxo, a.box_len, a.inv_box);
-                            dyo = min_img(dyo, a.box_len, a.inv_box);
-                            dzo = min_img(dzo, a.box_len, a.inv_box);
-                            dxn = min_img(dxn, a.box_len, a.inv_box);
-                            dyn = min_img(dyn, a.box_len, a.inv_box);
-                            dzn = min_img(dzn, a.box_len, a.inv_box);
-                        }
-                        const double kk = same ? a.k_intra : a.k_inter;
-                        acc += pair_d<FP64>(dxo, dyo, dzo, dxn, dyn, dzn, kk,
-                                            kk * L.ctab[bi_type(inf[s]) * kMaxTypes + tb]);
-                    }
-                    if (same) {
-                        double coef = 0.0;
-                        if (j == b - 2) coef = c_m2;
-                        if (j == b + 1) coef = c_p1;
-                        if (j == b - 3) coef = -ktors;
-                        if (j == b + 2) coef = ktors;
-                        acc += (AccP<FP64>)(coef * (ux[s] * mx + uy[s] * my + uz[s] * mz));
-                    }
+                const int d = j - b;
+                const bool same = chn[s] == cb;
+                const bool use = (j < N) && (d != 0) && !(same && (d == 1 || d == -1));
+                double dxo = px[s] - xbx, dyo = py[s] - xby, dzo = pz[s] - xbz;
+                double dxn = px[s] - nx, dyn = py[s] - ny, dzn = pz[s] - nz;
+                if constexpr (PERIODIC) {
+                    dxo = min_img(dxo, a.box_len, a.inv_box);
+                    dyo = min_img(dyo, a.box_len, a.inv_box);
+                    dzo = min_img(dzo, a.box_len, a.inv_box);
+                    dxn = min_img(dxn, a.box_len, a.inv_box);
+                    dyn = min_img(dyn, a.box_len, a.inv_box);
+                    dzn = min_img(dzn, a.box_len, a.inv_box);
                 }
+                const A fxo = (A)dxo, fyo = (A)dyo, fzo = (A)dzo;
+                const A fxn = (A)dxn, fyn = (A)dyn, fzn = (A)dzn;
+                A r2o = fxo * fxo + fyo * fyo + fzo * fzo;
+                A r2n = fxn * fxn + fyn * fyn + fzn * fzn;
+                r2o = use ? r2o : (A)1;
+                r2n = use ? r2n : (A)1;
+                A so, sn2;
+                if constexpr (FP64) {
+                    so = 1.0 / r2o; sn2 = 1.0 / r2n;
+                } else {
+                    so = __builtin_amdgcn_rcpf(r2o); sn2 = __builtin_amdgcn_rcpf(r2n);
+                }
+                const A s3o = so * so * so, s3n = sn2 * sn2 * sn2;
+                const A t = s3n * (kk[s].x * s3n - kk[s].y) - s3o * (kk[s].x * s3o - kk[s].y);
+                acc += use ? t : (A)0;
+                A coef = (d == -2) ? c_m2 : (A)0;
+                coef = (d == 1) ? c_p1 : coef;
+                coef = (d == -3) ? -ktors : coef;
+                coef = (d == 2) ? ktors : coef;
+                coef = same ? coef : (A)0;
+                acc += coef * (ux[s] * mxa + uy[s] * mya + uz[s] * mza);
             }
-            const double dE = half_sum(acc, hi);
+            const double dE = half_sum(acc);
             const double En = E + dE;
             const double t = (En - e_lo) * inv_eps;
             const bool inwin = (t >= 0.0) && (t < (double)K);
             const int kn = inwin ? (int)t : 0;
             const double lnw_new = lnw_at(L.lw, kn, En);
-            const bool accept = inwin && (hsel_d(lnu_l, i, hi) < lnw_new - lnw_cur);
+            const bool accept = inwin && (q.lnu < lnw_new - lnw_cur);
             n_wrej += inwin ? 0u : 1u;
             if (alog && (long long)n_mv < a.acc_log_moves && accept && gl == 0)
                 atomicOr(&alog[n_mv >> 5], 1u << (n_mv & 31));
             ++n_mv;
             if (accept) {
+                // bonds b-1 and b recomputed from the coordinates (no accumulated rounding)
+                const A bmx = (A)(nx - xmx), bmy = (A)(ny - xmy), bmz = (A)(nz - xmz);
+                const A bpx = (A)(xpx - nx), bpy = (A)(xpy - ny), bpz = (A)(xpz - nz);
 #pragma unroll
                 for (int s = 0; s < SLOTS; ++s) {
                     const int j = gl + kG * s;
-                    if (j == b - 1 && !fst) { ux[s] = nx - px[s]; uy[s] = ny - py[s]; uz[s] = nz - pz[s]; }
-                    if (j == b && !lst) { ux[s] -= mx; uy[s] -= my; uz[s] -= mz; }
+                    const bool lo_b = (j == b - 1) && !fst, at_b = (j == b) && !lst;
+                    ux[s] = lo_b ? bmx : (at_b ? bpx : ux[s]);
+                    uy[s] = lo_b ? bmy : (at_b ? bpy : uy[s]);
+                    uz[s] = lo_b ? bmz : (at_b ? bpz : uz[s]);
                     if (j == b) { px[s] = nx; py[s] = ny; pz[s] = nz; }
                 }
                 L.x[b] = nx; L.y[b] = ny; L.z[b] = nz;      // every lane of the half writes
@@ -329,7 +392,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                         const double tz = a.trans_max * (2.0 * u01(r1.w) - 1.0);
                         const double lnu_r = log(u01(r2.x));
                         const int cs = sd.chain_start[ch], ce = sd.chain_start[ch + 1];
-                        AccP<FP64> racc = 0;
+                        A racc = 0;
                         for (int ib = cs; ib < ce; ++ib) {
                             const double xi = L.x[ib], yi = L.y[ib], zi = L.z[ib];
                             const double xs = xi + tx, ys = yi + ty, zs = zi + tz;
@@ -337,7 +400,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
 #pragma unroll
                             for (int s = 0; s < SLOTS; ++s) {
                                 const int j = gl + kG * s;
-                                if (j < N && bi_chain(inf[s]) != ch) {
+                                if (j < N && chn[s] != ch) {
                                     double dxo = xi - px[s], dyo = yi - py[s], dzo = zi - pz[s];
                                     double dxn = xs - px[s], dyn = ys - py[s], dzn = zs - pz[s];
                                     if constexpr (PERIODIC) {
@@ -349,11 +412,11 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                                         dzn = min_img(dzn, a.box_len, a.inv_box);
                                     }
                                     racc += pair_d<FP64>(dxo, dyo, dzo, dxn, dyn, dzn, a.k_inter,
-                                                         a.k_inter * L.ctab[bi_type(inf[s]) * kMaxTypes + ti]);
+                                                         a.k_inter * L.ctab[trow[s] + ti]);
                                 }
                             }
                         }
-                        const double rdE = half_sum(racc, hi);
+                        const double rdE = half_sum(racc);
                         const double rEn = E + rdE;
                         const double rt = (rEn - e_lo) * inv_eps;
                         const bool rin = (rt >= 0.0) && (rt < (double)K);
@@ -365,7 +428,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                         if (rok) {
 #pragma unroll
                             for (int s = 0; s < SLOTS; ++s)
-                                if (bi_chain(inf[s]) == ch) { px[s] += tx; py[s] += ty; pz[s] += tz; }
+                                if (chn[s] == ch) { px[s] += tx; py[s] += ty; pz[s] += tz; }
                             for (int ib = cs; ib < ce; ++ib) {     // every lane of the half writes
                                 const double xo = L.x[ib], yo = L.y[ib], zo = L.z[ib];
                                 L.x[ib] = xo + tx; L.y[ib] = yo + ty; L.z[ib] = zo + tz;
@@ -382,7 +445,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 }
                 ++S;
                 if (a.resync_sweeps > 0 && (S % (unsigned long long)a.resync_sweeps) == 0) {
-                    const double Ef = full_energy_pair<SLOTS, PERIODIC>(a, N, L, px, py, pz, inf, hi);
+                    const double Ef = full_energy_pair<SLOTS, PERIODIC>(a, N, L, px, py, pz, inf);
                     const double dr = fabs(Ef - E);
                     max_drift = fmax(max_drift, dr);
                     if (dr > a.drift_tol && gl == 0) set_error(a.err, -5);
@@ -402,6 +465,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             }
         }
         done += nblk;
+        __builtin_amdgcn_wave_barrier();        // staged entries are rewritten by the next block
     }
     if (gl == 0 && run) atomicAdd(&L.hist[k], (unsigned long long)run);
 
@@ -424,22 +488,32 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
 
 }  // namespace
 
+constexpr int kStage = kG + 1;   // staged moves per walker (+1 spare for the prefetch)
+
 // LDS layout (per workgroup): (beta_k, alpha_k) of every system of the workgroup at bin offset
-// lds_off[i], the C_LJ table, the x, y and z coordinate mirrors of every walker (stride
-// pos_stride) and the bead descriptors of every system.
+// lds_off[i]; the C_LJ table; the {kappa, kappa C_LJ} table (intra, inter) in the accumulator
+// type; the staged draws of every walker; the x, y and z coordinate mirrors of every walker
+// (stride pos_stride); the staged bead indices of every walker; the bead descriptors of every
+// system.
 template <bool FP64, int SLOTS, bool PERIODIC>
 __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_sweeps, int pos_stride) {
+    using A = AccP<FP64>;
+    using A2 = typename std::conditional<FP64, double2, float2>::type;
     extern __shared__ double2 lds_p[];
     const WorkItem &wi = a.work[blockIdx.x];
     const int ns = wi.n_sys;
     const int n_waves = blockDim.x >> 6;
+    const int n_wl = 2 * n_waves;
     const int bins_total = wi.lds_off[ns - 1] + a.sys[wi.sys[ns - 1]].n_bins;
     double2 *lw = lds_p;
     double *ctab = reinterpret_cast<double *>(lw + bins_total);
-    double *px = ctab + kMaxTypes * kMaxTypes;
-    double *py = px + (size_t)2 * n_waves * pos_stride;
-    double *pz = py + (size_t)2 * n_waves * pos_stride;
-    int *binfo = reinterpret_cast<int *>(pz + (size_t)2 * n_waves * pos_stride);
+    A2 *kc = reinterpret_cast<A2 *>(ctab + kMaxTypes * kMaxTypes);
+    Staged *sq = reinterpret_cast<Staged *>(reinterpret_cast<double2 *>(kc) + 2 * kMaxTypes * kMaxTypes);
+    double *px = reinterpret_cast<double *>(sq + (size_t)n_wl * kStage);
+    double *py = px + (size_t)n_wl * pos_stride;
+    double *pz = py + (size_t)n_wl * pos_stride;
+    int *sb = reinterpret_cast<int *>(pz + (size_t)n_wl * pos_stride);
+    int *binfo = sb + n_wl * kStage;
     for (int i = 0; i < ns; ++i) {
         const SysDev &sd = a.sys[wi.sys[i]];
         const int off = wi.lds_off[i];
@@ -448,9 +522,16 @@ __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_swe
         for (int j = threadIdx.x; j < kMaxBeads; j += blockDim.x)
             binfo[i * kMaxBeads + j] = a.binfo[wi.sys[i] * kMaxBeads + j];
     }
-    if (threadIdx.x < kMaxTypes * kMaxTypes) {
-        const int t = threadIdx.x / kMaxTypes, u = threadIdx.x % kMaxTypes;
-        ctab[threadIdx.x] = (t < a.n_types && u < a.n_types) ? a.c_lj[t * a.n_types + u] : 0.0;
+    if (threadIdx.x < 2 * kMaxTypes * kMaxTypes) {
+        const int e = threadIdx.x % (kMaxTypes * kMaxTypes);
+        const int t = e / kMaxTypes, u = e % kMaxTypes;
+        const double c = (t < a.n_types && u < a.n_types) ? a.c_lj[t * a.n_types + u] : 0.0;
+        const double kap = threadIdx.x < kMaxTypes * kMaxTypes ? a.k_intra : a.k_inter;
+        if (threadIdx.x < kMaxTypes * kMaxTypes) ctab[e] = c;
+        A2 v;
+        v.x = (A)kap;
+        v.y = (A)(kap * c);
+        kc[threadIdx.x] = v;
     }
     const int wave = threadIdx.x >> 6;
     const bool hi = (threadIdx.x & 63) >= 32;
@@ -478,13 +559,18 @@ __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_swe
         L.y = py + (size_t)wl * pos_stride;
         L.z = pz + (size_t)wl * pos_stride;
         L.ctab = ctab;
+        L.kc = kc;
+        L.sb = sb + wl * kStage;
+        L.sq = sq + (size_t)wl * kStage;
         run_pair<FP64, SLOTS, PERIODIC>(a, sd, w0 + (hi ? 1 : 0), L, n_sweeps);
     }
 }
 
 size_t sweep_pair_lds_bytes(long long bins_total, int n_sys, int n_waves, int pos_stride) {
-    return 2 * sizeof(double) * (size_t)bins_total +
-           sizeof(double) * ((size_t)kMaxTypes * kMaxTypes + (size_t)3 * 2 * n_waves * pos_stride) +
+    const size_t n_wl = 2 * (size_t)n_waves;
+    return 2 * sizeof(double) * (size_t)bins_total + sizeof(double) * kMaxTypes * kMaxTypes +
+           2 * sizeof(double2) * kMaxTypes * kMaxTypes + sizeof(Staged) * n_wl * kStage +
+           3 * sizeof(double) * n_wl * (size_t)pos_stride + sizeof(int) * n_wl * kStage +
            sizeof(int) * (size_t)n_sys * kMaxBeads;
 }
 

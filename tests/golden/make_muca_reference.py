@@ -20,7 +20,7 @@ import oracle  # noqa: E402
 import workloads  # noqa: E402
 from oracle import analysis  # noqa: E402
 
-REPLICAS, WALKERS, ITERS, SWEEPS, BLOCK = 12, 4, 12, 20000, 4
+REPLICAS, WALKERS, ITERS, SWEEPS, BLOCK = 32, 4, 12, 20000, 4
 SEED0 = 500
 
 

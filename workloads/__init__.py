@@ -141,6 +141,7 @@ def batched_chains(seed: int = 1702, n_seq: int = 32, n_min: int = 13, n_max: in
     systems = [_single_chain_system(ab_sequence(rng, int(n)), 0.05) for n in lens]
     return Workload(name=f"batched_{n_seq}seq_{n_min}-{n_max}", systems=systems,
                     walkers_per_system=walkers // n_seq, precision=precision, seed=seed,
+                    resync_sweeps=100 if precision == PREC_FP32_SPLIT else 0,
                     n_iter=n_iter, n_sweeps=n_sweeps)
 
 
