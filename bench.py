@@ -29,14 +29,15 @@ PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (published, packed)
 
 def algorithmic_flops_per_move(n_beads: int, n_chains: int = 1, periodic: bool = False,
                                torsion: bool = False) -> float:
-    """Operations a single-bead trial move must perform (Measurement):
-    per non-bonded partner two pair-term evaluations (separation 3, r^2 5, reciprocal 1, s^3 2,
-    kappa s^3 (s^3 - C) 3 = 14 each; +9 each for the periodic minimum image) plus difference
-    and accumulation (2); 60 for proposal, bending terms and acceptance, +40 with torsion."""
+    """Operations a single-bead trial move must perform (no Newton refinements, no masked
+    work): per non-bonded partner two pair-term evaluations (separation 3, r^2 5, reciprocal 1,
+    s^3 2, s^3 (kappa s^3 - kappa C) 2 = 13 each; +9 each for the periodic minimum image) plus
+    their difference and the accumulation (2); 50 for the bending terms, +56 with torsion; 60 for
+    building the proposal and the acceptance test."""
     bonded = (2 * (n_beads - 2 * n_chains) + 2 * n_chains) / n_beads   # mean bonded neighbours
     partners = n_beads - 1 - bonded
-    per_pair = 2 * (14 + (9 if periodic else 0)) + 2
-    return partners * per_pair + 60 + (40 if torsion else 0)
+    per_pair = 2 * (13 + (9 if periodic else 0)) + 2
+    return partners * per_pair + 50 + 60 + (56 if torsion else 0)
 
 
 _STREAMS = []

@@ -64,8 +64,12 @@ enum { MUCA_PREC_FP64 = 0, MUCA_PREC_FP32_SPLIT = 1 };
  * waves_per_block: wavefronts per workgroup (0 = library default); walkers_per_wave: 1 runs
  * one walker per 64-lane wavefront, 2 runs two walkers of a system in the two 32-lane halves of
  * a wavefront (needs an even walkers_per_system and at most 8 waves per block), 0 lets the
- * library choose (2 when possible).  Neither changes any result: every walker's trajectory
- * depends only on its seed and walker index.  stream: a hipStream_t to run on, or NULL for a
+ * library choose (2 when possible).  Two walkers per wave read ln W from its values at the bin
+ * edges, which needs continuous weights (the two lines of Eq. 8 meeting at every inner bin edge
+ * agree there, as the weight recursion maintains); weights set through muca_set_weights or
+ * muca_set_state that are not switch the context to one walker per wave until continuous ones
+ * are set again.  Neither setting changes any result: every walker's trajectory depends only on
+ * its seed and walker index.  stream: a hipStream_t to run on, or NULL for a
  * stream created and owned by the context.
  */
 typedef struct {

@@ -157,4 +157,16 @@ __device__ __forceinline__ int wave_min_i(int v) {
 
 __device__ __forceinline__ void set_error(int *err, int code) { atomicCAS(err, 0, code); }
 
+// Bin of energy e in the window [e_lo, e_lo + K eps), or -1.  A walker whose running energy sat
+// at a window edge can be found up to a few 1e-5 outside it by the FP64 resync (FP32 pair terms
+// accumulate rounding between resyncs); energies within kEdgeTol outside the window are kept in
+// the edge bin, so the walker continues from its exact energy.
+constexpr double kEdgeTol = 1e-3;
+__device__ __forceinline__ int window_bin(double e, double e_lo, double eps, double inv_eps, int K) {
+    const double t = (e - e_lo) * inv_eps;
+    if (t >= 0.0 && t < (double)K) return (int)t;
+    if (e >= e_lo - kEdgeTol && e < e_lo + (double)K * eps + kEdgeTol) return t < 0.0 ? 0 : K - 1;
+    return -1;
+}
+
 }  // namespace muca

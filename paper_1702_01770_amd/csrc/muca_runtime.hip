@@ -59,6 +59,8 @@ struct muca_ctx {
     int pack = 1;              // walkers per wave: 1 (k_sweep) or 2 (k_sweep_pair)
     int pos_stride = 0;        // LDS coordinate stride of k_sweep_pair
     int pair_slots = 1;        // bead slots per lane of k_sweep_pair (32 lanes per walker)
+    bool weights_continuous = true;   // ln W continuous at every bin edge (k_sweep_pair needs it)
+    bool pack_fallback = false;       // one walker per wave because of discontinuous weights
     bool paired = true;
     size_t lds_limit = 0;
     size_t lds_bytes = 0;
@@ -204,6 +206,37 @@ static int build_schedule(muca_ctx *ctx, int wpb, bool pair, int pack) {
     ctx->lds_bytes = lds_max;
     ctx->args.work = ctx->d_work;
     drop_graphs(ctx);
+    return MUCA_OK;
+}
+
+// k_sweep_pair interpolates ln W between its bin-edge values, which is Eq. 8 when the lines of
+// neighbouring bins meet at their common edge.  The Berg recursion keeps that property; weights
+// set from the host are checked here, and a context holding discontinuous weights runs one walker
+// per wave (k_sweep reads beta_k, alpha_k directly) until continuous ones are set again.
+static int refresh_continuity(muca_ctx *ctx) {
+    std::vector<double> b(ctx->total_bins), al(ctx->total_bins);
+    CK(hipMemcpy(b.data(), ctx->d_beta, sizeof(double) * b.size(), hipMemcpyDeviceToHost));
+    CK(hipMemcpy(al.data(), ctx->d_alpha, sizeof(double) * al.size(), hipMemcpyDeviceToHost));
+    bool ok = true;
+    for (const SysHost &h : ctx->sys) {
+        for (int k = 0; k + 1 < h.n_bins && ok; ++k) {
+            const double e = h.e_lo + (double)(k + 1) * ctx->args.bin_width;
+            const double l0 = -b[h.bin_off + k] * e + al[h.bin_off + k];
+            const double l1 = -b[h.bin_off + k + 1] * e + al[h.bin_off + k + 1];
+            if (!(std::fabs(l0 - l1) <= 1e-9 * std::max(1.0, std::max(std::fabs(l0), std::fabs(l1)))))
+                ok = false;
+        }
+    }
+    ctx->weights_continuous = ok;
+    if (!ok && ctx->pack == 2) {
+        const int rc = build_schedule(ctx, std::min(16, ctx->W), true, 1);
+        if (rc != MUCA_OK) return rc;
+        ctx->pack_fallback = true;
+    } else if (ok && ctx->pack_fallback) {
+        const int rc = build_schedule(ctx, std::max(1, std::min(8, ctx->W / 2)), true, 2);
+        if (rc == MUCA_OK) ctx->pack_fallback = false;
+        else ctx->err.clear();          // keep one walker per wave
+    }
     return MUCA_OK;
 }
 
@@ -648,7 +681,7 @@ int muca_set_weights(muca_ctx *ctx, int32_t sys, const double *beta, const doubl
     if (beta) CK(hipMemcpy(ctx->d_beta + off, beta, sizeof(double) * n, hipMemcpyHostToDevice));
     if (alpha) CK(hipMemcpy(ctx->d_alpha + off, alpha, sizeof(double) * n, hipMemcpyHostToDevice));
     if (g) CK(hipMemcpy(ctx->d_g + off, g, sizeof(double) * n, hipMemcpyHostToDevice));
-    return MUCA_OK;
+    return refresh_continuity(ctx);
 }
 
 int muca_get_walkers(muca_ctx *ctx, int32_t sys, double *pos, double *energy,
@@ -822,7 +855,7 @@ int muca_set_state(muca_ctx *ctx, const void *buf, size_t bytes) {
     CK(put(ctx->d_hist, sizeof(unsigned long long) * nb));
     CK(put(ctx->d_hist_last, sizeof(unsigned long long) * nb));
     CK(put(ctx->d_iter, sizeof(long long)));
-    return MUCA_OK;
+    return refresh_continuity(ctx);
 }
 
 static int energy_args(muca_ctx *ctx, int32_t sys, const float *x, int64_t n_cfg,
@@ -910,7 +943,7 @@ int muca_autotune(muca_ctx *ctx, int64_t probe_sweeps, int32_t *chosen) {
     struct Cand { int pack, wpb; bool pair; };
     std::vector<Cand> cands;
     for (int pack = 2; pack >= 1; --pack) {
-        if (pack == 2 && ctx->W % 2 != 0) continue;
+        if (pack == 2 && (ctx->W % 2 != 0 || !ctx->weights_continuous)) continue;
         for (int pr = 1; pr >= 0; --pr)
             for (int c : {16, 8, 4, 2, 1}) {
                 if (pack == 2 && c > 8) continue;

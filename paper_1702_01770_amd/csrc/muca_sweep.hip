@@ -188,11 +188,8 @@ __device__ void run_walker(const SweepArgs &a, const SysDev &sd, int sys, int w,
     unsigned long long S = cnt[C_SWEEPS];
     const unsigned int k0 = a.seed_lo, k1 = a.seed_hi ^ (unsigned int)w;
     int k;
-    {
-        double t = (E - e_lo) * a.inv_bin;
-        if (!(t >= 0.0 && t < (double)K)) { set_error(a.err, -4); return; }
-        k = (int)t;
-    }
+    k = window_bin(E, e_lo, a.bin_width, a.inv_bin, K);
+    if (k < 0) { set_error(a.err, -4); return; }
     double2 wk = lnw[k];
     double lnw_cur = -wk.x * E + wk.y;
 
@@ -398,9 +395,8 @@ __device__ void run_walker(const SweepArgs &a, const SysDev &sd, int sys, int w,
                     const double dr = fabs(Ef - E);
                     max_drift = fmax(max_drift, dr);
                     if (dr > a.drift_tol) set_error(a.err, -5);
-                    const double tf = (Ef - e_lo) * a.inv_bin;
-                    if (tf >= 0.0 && tf < (double)K) {
-                        const int kf = (int)tf;
+                    const int kf = window_bin(Ef, e_lo, a.bin_width, a.inv_bin, K);
+                    if (kf >= 0) {
                         if (kf != k) {
                             if (lane == 0) atomicAdd(&hist[k], run);
                             run = 0;

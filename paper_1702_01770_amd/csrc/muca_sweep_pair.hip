@@ -8,9 +8,12 @@
 // Coordinates are mirrored in LDS so that each half can read "its" moved bead and neighbours
 // with ordinary LDS loads; every update of a bead is written by all 32 lanes of its half, so a
 // lane never reads an LDS word that it has not written itself after the initial barrier.
-// ln W is read from the (beta_k, alpha_k) pairs of Eq. 8 staged in LDS, as in k_sweep; the
-// histogram is accumulated run-length encoded straight into device memory (one atomic add per
-// change of bin), which leaves the LDS to the tables and the coordinate mirror.
+// ln W (Eq. 8) is continuous and linear inside each bin, so LDS holds its values at the K + 1 bin
+// edges (8 bytes per bin) and a move reads the two edges of its bin with one ds_read2; the
+// runtime uses this kernel only for weights that are continuous (the Berg recursion keeps them
+// so).  That leaves room for a private 32-bit histogram per system in LDS, counted run-length
+// encoded (one LDS atomic whenever a walker changes bin) and added to the device histogram once
+// per launch.
 #include <type_traits>
 
 #include "muca_device.h"
@@ -80,10 +83,11 @@ __device__ __forceinline__ double half_sum_f(float v) {
 __device__ __forceinline__ double half_sum(double v) { return half_sum_d(v); }
 __device__ __forceinline__ double half_sum(float v) { return half_sum_f(v); }
 
-// ln W(E) = -beta_k E + alpha_k in bin k (Eq. 8)
-__device__ __forceinline__ double lnw_at(const double2 *lw, int k, double e) {
-    const double2 w = lw[k];
-    return -w.x * e + w.y;
+// ln W at t = (E - E_lo) / eps in bin k (t in [k, k+1) except at a tolerated window edge, where
+// the bin's line is extended), from the edge values le[k], le[k+1]
+__device__ __forceinline__ double lnw_at(const double *le, int k, double t) {
+    const double l0 = le[k], l1 = le[k + 1];
+    return l0 + (l1 - l0) * (t - (double)k);
 }
 
 // Per-move values drawn ahead by the lanes of a half (one move per lane) and read back by the
@@ -93,8 +97,8 @@ struct Staged {
 };
 
 struct PairLds {
-    const double2 *lw;         // (beta_k, alpha_k) of this walker's system
-    unsigned long long *hist;  // device histogram of this walker's system
+    const double *lw;          // ln W at the K + 1 bin edges of this walker's system
+    unsigned int *hist;        // LDS histogram of this walker's system
     const int *binfo;          // bead descriptors of this walker's system
     double *x, *y, *z;         // this walker's coordinates
     const double *ctab;        // C_LJ[t][u], t, u < kMaxTypes
@@ -203,16 +207,12 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
     unsigned long long *cnt = a.cnt + (size_t)w * C_NCOUNT;
     unsigned long long S = cnt[C_SWEEPS];
     const unsigned int k0 = a.seed_lo, k1 = a.seed_hi ^ (unsigned int)w;
-    int k;
-    {
-        const double t = (E - e_lo) * inv_eps;
-        if (!(t >= 0.0 && t < (double)K)) {      // this half's walker does no work
-            if (gl == 0) set_error(a.err, -4);
-            return;
-        }
-        k = (int)t;
+    int k = window_bin(E, e_lo, a.bin_width, inv_eps, K);
+    if (k < 0) {                                // this half's walker does no work
+        if (gl == 0) set_error(a.err, -4);
+        return;
     }
-    double lnw_cur = lnw_at(L.lw, k, E);
+    double lnw_cur = lnw_at(L.lw, k, (E - e_lo) * inv_eps);
 
     unsigned int n_mv = 0, n_acc = 0, n_rig = 0, n_rig_acc = 0, n_wrej = 0, run = 0;
     double max_drift = a.drift[w];
@@ -313,7 +313,9 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 const int j = gl + kG * s;
                 const int d = j - b;
                 const bool same = chn[s] == cb;
-                const bool use = (j < N) && (d != 0) && !(same && (d == 1 || d == -1));
+                // skip the moved bead itself (d = 0, same chain), its bonded neighbours and empty
+                // lanes
+                const bool use = (j < N) && !(same && (unsigned)(d + 1) <= 2u);
                 double dxo = px[s] - xbx, dyo = py[s] - xby, dzo = pz[s] - xbz;
                 double dxn = px[s] - nx, dyn = py[s] - ny, dzn = pz[s] - nz;
                 if constexpr (PERIODIC) {
@@ -351,7 +353,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             const double t = (En - e_lo) * inv_eps;
             const bool inwin = (t >= 0.0) && (t < (double)K);
             const int kn = inwin ? (int)t : 0;
-            const double lnw_new = lnw_at(L.lw, kn, En);
+            const double lnw_new = lnw_at(L.lw, kn, t);
             const bool accept = inwin && (q.lnu < lnw_new - lnw_cur);
             n_wrej += inwin ? 0u : 1u;
             if (alog && (long long)n_mv < a.acc_log_moves && accept && gl == 0)
@@ -372,7 +374,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 }
                 L.x[b] = nx; L.y[b] = ny; L.z[b] = nz;      // every lane of the half writes
                 if (kn != k) {
-                    if (gl == 0) atomicAdd(&L.hist[k], (unsigned long long)run);
+                    if (gl == 0) atomicAdd(&L.hist[k], run);
                     run = 0;
                 }
                 E = En; k = kn; lnw_cur = lnw_new;
@@ -421,7 +423,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                         const double rt = (rEn - e_lo) * inv_eps;
                         const bool rin = (rt >= 0.0) && (rt < (double)K);
                         const int rkn = rin ? (int)rt : 0;
-                        const double rlnw = lnw_at(L.lw, rkn, rEn);
+                        const double rlnw = lnw_at(L.lw, rkn, rt);
                         const bool rok = rin && (lnu_r < rlnw - lnw_cur);
                         n_wrej += rin ? 0u : 1u;
                         ++n_rig;
@@ -434,7 +436,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                                 L.x[ib] = xo + tx; L.y[ib] = yo + ty; L.z[ib] = zo + tz;
                             }
                             if (rkn != k) {
-                                if (gl == 0) atomicAdd(&L.hist[k], (unsigned long long)run);
+                                if (gl == 0) atomicAdd(&L.hist[k], run);
                                 run = 0;
                             }
                             E = rEn; k = rkn; lnw_cur = rlnw;
@@ -449,15 +451,14 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                     const double dr = fabs(Ef - E);
                     max_drift = fmax(max_drift, dr);
                     if (dr > a.drift_tol && gl == 0) set_error(a.err, -5);
-                    const double tf = (Ef - e_lo) * inv_eps;
-                    if (tf >= 0.0 && tf < (double)K) {
-                        const int kf = (int)tf;
+                    const int kf = window_bin(Ef, e_lo, a.bin_width, inv_eps, K);
+                    if (kf >= 0) {
                         if (kf != k) {
-                            if (gl == 0) atomicAdd(&L.hist[k], (unsigned long long)run);
+                            if (gl == 0) atomicAdd(&L.hist[k], run);
                             run = 0;
                         }
                         E = Ef; k = kf;
-                        lnw_cur = lnw_at(L.lw, k, E);
+                        lnw_cur = lnw_at(L.lw, k, (E - e_lo) * inv_eps);
                     } else if (gl == 0) {
                         set_error(a.err, -4);
                     }
@@ -467,7 +468,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
         done += nblk;
         __builtin_amdgcn_wave_barrier();        // staged entries are rewritten by the next block
     }
-    if (gl == 0 && run) atomicAdd(&L.hist[k], (unsigned long long)run);
+    if (gl == 0 && run) atomicAdd(&L.hist[k], run);
 
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -490,11 +491,11 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
 
 constexpr int kStage = kG + 1;   // staged moves per walker (+1 spare for the prefetch)
 
-// LDS layout (per workgroup): (beta_k, alpha_k) of every system of the workgroup at bin offset
-// lds_off[i]; the C_LJ table; the {kappa, kappa C_LJ} table (intra, inter) in the accumulator
-// type; the staged draws of every walker; the x, y and z coordinate mirrors of every walker
-// (stride pos_stride); the staged bead indices of every walker; the bead descriptors of every
-// system.
+// LDS layout (per workgroup), 16-byte items first: the {kappa, kappa C_LJ} table (intra, inter)
+// in the accumulator type; the staged draws of every walker; the C_LJ table; the x, y and z
+// coordinate mirrors of every walker (stride pos_stride); ln W at the bin edges of every system
+// of the workgroup (system i at lds_off[i] + i); the 32-bit histograms (system i at lds_off[i]);
+// the staged bead indices of every walker; the bead descriptors of every system.
 template <bool FP64, int SLOTS, bool PERIODIC>
 __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_sweeps, int pos_stride) {
     using A = AccP<FP64>;
@@ -505,20 +506,27 @@ __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_swe
     const int n_waves = blockDim.x >> 6;
     const int n_wl = 2 * n_waves;
     const int bins_total = wi.lds_off[ns - 1] + a.sys[wi.sys[ns - 1]].n_bins;
-    double2 *lw = lds_p;
-    double *ctab = reinterpret_cast<double *>(lw + bins_total);
-    A2 *kc = reinterpret_cast<A2 *>(ctab + kMaxTypes * kMaxTypes);
-    Staged *sq = reinterpret_cast<Staged *>(reinterpret_cast<double2 *>(kc) + 2 * kMaxTypes * kMaxTypes);
-    double *px = reinterpret_cast<double *>(sq + (size_t)n_wl * kStage);
+    A2 *kc = reinterpret_cast<A2 *>(lds_p);
+    Staged *sq = reinterpret_cast<Staged *>(lds_p + 2 * kMaxTypes * kMaxTypes);
+    double *ctab = reinterpret_cast<double *>(sq + (size_t)n_wl * kStage);
+    double *px = ctab + kMaxTypes * kMaxTypes;
     double *py = px + (size_t)n_wl * pos_stride;
     double *pz = py + (size_t)n_wl * pos_stride;
-    int *sb = reinterpret_cast<int *>(pz + (size_t)n_wl * pos_stride);
+    double *lw = pz + (size_t)n_wl * pos_stride;
+    unsigned int *hist = reinterpret_cast<unsigned int *>(lw + bins_total + ns);
+    int *sb = reinterpret_cast<int *>(hist + bins_total);
     int *binfo = sb + n_wl * kStage;
     for (int i = 0; i < ns; ++i) {
         const SysDev &sd = a.sys[wi.sys[i]];
         const int off = wi.lds_off[i];
-        for (int kk = threadIdx.x; kk < sd.n_bins; kk += blockDim.x)
-            lw[off + kk] = make_double2(a.beta[sd.bin_off + kk], a.alpha[sd.bin_off + kk]);
+        const int K = sd.n_bins;
+        for (int kk = threadIdx.x; kk <= K; kk += blockDim.x) {
+            // ln W at the lower edge of bin kk from bin kk's line; the top edge from the last bin
+            const int kb = kk < K ? kk : K - 1;
+            const double e = sd.e_lo + (double)kk * a.bin_width;
+            lw[off + i + kk] = -a.beta[sd.bin_off + kb] * e + a.alpha[sd.bin_off + kb];
+            if (kk < K) hist[off + kk] = 0u;
+        }
         for (int j = threadIdx.x; j < kMaxBeads; j += blockDim.x)
             binfo[i * kMaxBeads + j] = a.binfo[wi.sys[i] * kMaxBeads + j];
     }
@@ -552,8 +560,8 @@ __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_swe
         const int sys = wi.sys[i];
         const SysDev &sd = a.sys[sys];
         PairLds L;
-        L.lw = lw + wi.lds_off[i];
-        L.hist = a.hist + sd.bin_off;
+        L.lw = lw + wi.lds_off[i] + i;
+        L.hist = hist + wi.lds_off[i];
         L.binfo = binfo + i * kMaxBeads;
         L.x = px + (size_t)wl * pos_stride;
         L.y = py + (size_t)wl * pos_stride;
@@ -564,14 +572,23 @@ __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_swe
         L.sq = sq + (size_t)wl * kStage;
         run_pair<FP64, SLOTS, PERIODIC>(a, sd, w0 + (hi ? 1 : 0), L, n_sweeps);
     }
+    __syncthreads();
+    for (int i = 0; i < ns; ++i) {
+        const SysDev &sd = a.sys[wi.sys[i]];
+        const int off = wi.lds_off[i];
+        for (int kk = threadIdx.x; kk < sd.n_bins; kk += blockDim.x) {
+            const unsigned int h = hist[off + kk];
+            if (h) atomicAdd(&a.hist[sd.bin_off + kk], (unsigned long long)h);
+        }
+    }
 }
 
 size_t sweep_pair_lds_bytes(long long bins_total, int n_sys, int n_waves, int pos_stride) {
     const size_t n_wl = 2 * (size_t)n_waves;
-    return 2 * sizeof(double) * (size_t)bins_total + sizeof(double) * kMaxTypes * kMaxTypes +
-           2 * sizeof(double2) * kMaxTypes * kMaxTypes + sizeof(Staged) * n_wl * kStage +
-           3 * sizeof(double) * n_wl * (size_t)pos_stride + sizeof(int) * n_wl * kStage +
-           sizeof(int) * (size_t)n_sys * kMaxBeads;
+    return 2 * sizeof(double2) * kMaxTypes * kMaxTypes + sizeof(Staged) * n_wl * kStage +
+           sizeof(double) * kMaxTypes * kMaxTypes + 3 * sizeof(double) * n_wl * (size_t)pos_stride +
+           sizeof(double) * (size_t)(bins_total + n_sys) + sizeof(unsigned int) * (size_t)bins_total +
+           sizeof(int) * n_wl * kStage + sizeof(int) * (size_t)n_sys * kMaxBeads;
 }
 
 template <bool FP64, int SLOTS, bool PERIODIC>

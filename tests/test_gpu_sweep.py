@@ -236,3 +236,62 @@ def test_drift_detector_fires_on_corrupted_energy(lib):
         m.synchronize()
     assert "DRIFT" in str(ei.value)
     m.close()
+
+
+@pytest.mark.parametrize("pack", [1, 2])
+def test_window_edge_tolerance(lib, pack):
+    """A running energy up to 1e-3 outside the window (what FP32 accumulation can leave at an edge
+    until the next FP64 resync) is kept in the edge bin; further outside it is an error."""
+    import struct
+    wl = workloads.single_chain()
+    sp = wl.systems[0]
+    e_hi = sp.e_lo + sp.n_bins * wl.bin_width
+    for offset, ok in ((5e-4, True), (1e-2, False)):
+        m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=2, precision=1,
+                                   resync_sweeps=10, walkers_per_wave=pack)
+        blob = bytearray(m.get_state())
+        hdr = struct.unpack_from("6Q", blob, 0)
+        struct.pack_into("d", blob, 48 + 8 * hdr[2], e_hi + offset)
+        m.set_state(bytes(blob))
+        m.sweep(20)
+        if ok:
+            m.synchronize()
+            _, e, _ = m.walkers_state(0)
+            assert np.all(e < e_hi)                    # resync restored the exact energy
+        else:
+            with pytest.raises(lib.MucaError) as ei:
+                m.synchronize()
+            assert "WINDOW" in str(ei.value)
+        m.close()
+
+
+def test_discontinuous_weights_fall_back_to_one_walker_per_wave(lib, orc):
+    """Two walkers per wave read ln W from its bin-edge values, which needs continuous weights.
+    Random (discontinuous) beta, alpha switch the context to one walker per wave, whose sweep still
+    matches the oracle move for move; continuous weights switch it back."""
+    wl = workloads.single_chain()
+    sp = wl.systems[0]
+    rng = np.random.default_rng(5)
+    beta = rng.uniform(0.0, 0.5, sp.n_bins)
+    alpha = rng.uniform(-2.0, 2.0, sp.n_bins)
+    g = np.zeros(sp.n_bins)
+    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=4, precision=0)
+    assert m.launch_info()["walkers_per_wave"] == 2
+    m.set_weights(0, beta, alpha, g)
+    assert m.launch_info()["walkers_per_wave"] == 1
+    n_sweeps = 500
+    m.set_accept_log(n_sweeps * sp.n_beads)
+    m.sweep(n_sweeps)
+    W = orc.Weights(sp.e_lo, wl.bin_width, sp.n_bins, beta, alpha, g)
+    H, ows = _oracle_walkers(orc, wl, 0, 4, n_sweeps, W, log_moves=n_sweeps * sp.n_beads)
+    assert np.array_equal(m.histogram(0), H)
+    log_g = m.accept_log(0)
+    pos_g, e_g, _ = m.walkers_state(0)
+    for i, (ow, olog) in enumerate(ows):
+        assert np.array_equal(log_g[i], olog)
+        assert np.allclose(pos_g[i], ow.pos, rtol=0, atol=1e-10)
+    res = orc.muca(wl, n_iter=2, n_sweeps=2000, walkers=2)
+    Wc = res["weights"]
+    m.set_weights(0, Wc.beta, Wc.alpha, Wc.g)
+    assert m.launch_info()["walkers_per_wave"] == 2
+    m.close()
