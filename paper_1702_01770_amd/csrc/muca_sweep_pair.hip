@@ -103,7 +103,7 @@ struct PairLds {
     double *x, *y, *z;         // this walker's coordinates
     const double *ctab;        // C_LJ[t][u], t, u < kMaxTypes
     const void *kc;            // {kappa, kappa C_LJ}[intra / inter][t][u] in the accumulator type
-    int *sb;                   // staged bead index of the next kG moves (+1 spare)
+    int2 *sb;                  // staged bead index and descriptor of the next kG moves (+1 spare)
     Staged *sq;                // staged random values of the next kG moves (+1 spare)
 };
 
@@ -246,30 +246,23 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 q.q2 = 0.0;
             }
             q.lnu = log(u3);
-            L.sb[gl] = blane;
+            L.sb[gl] = make_int2(blane, binf_l);
             L.sq[gl] = q;
-            if (gl == 0) L.sb[kG] = 0;      // spare entry read by the prefetch of the last move
+            if (gl == 0) L.sb[kG] = make_int2(0, L.binfo[0]);   // spare entry for the last prefetch
             __builtin_amdgcn_wave_barrier();
         }
-        int b_nx = L.sb[0];
-        int inf_nx = L.binfo[b_nx];
-        A2 kk_nx[SLOTS];
-#pragma unroll
-        for (int s = 0; s < SLOTS; ++s)
-            kk_nx[s] = kct[(chn[s] == bi_chain(inf_nx) ? 0 : kMaxTypes * kMaxTypes) + trow[s] + bi_type(inf_nx)];
+        int2 bi_nx = L.sb[0];
 
         for (int i = 0; i < nblk; ++i) {
-            const int b = b_nx, infb = inf_nx;
+            // everything read here depends only on the staged draw of this move, so all of it is
+            // in flight at once; the draw of the next move is read now as well
+            const int b = bi_nx.x, infb = bi_nx.y;
+            const Staged q = L.sq[i];
+            bi_nx = L.sb[i + 1];
             A2 kk[SLOTS];
 #pragma unroll
-            for (int s = 0; s < SLOTS; ++s) kk[s] = kk_nx[s];
-            const Staged q = L.sq[i];
-            b_nx = L.sb[i + 1];                 // prefetch: the draws do not depend on this move
-            inf_nx = L.binfo[b_nx];
-#pragma unroll
             for (int s = 0; s < SLOTS; ++s)
-                kk_nx[s] = kct[(chn[s] == bi_chain(inf_nx) ? 0 : kMaxTypes * kMaxTypes) + trow[s] +
-                               bi_type(inf_nx)];
+                kk[s] = kct[(chn[s] == bi_chain(infb) ? 0 : kMaxTypes * kMaxTypes) + trow[s] + bi_type(infb)];
             const int tb = bi_type(infb), cb = bi_chain(infb);
             const bool fst = bi_first(infb), lst = bi_last(infb);
             const int bm = fst ? b : b - 1, bp = lst ? b : b + 1;
@@ -494,8 +487,8 @@ constexpr int kStage = kG + 1;   // staged moves per walker (+1 spare for the pr
 // LDS layout (per workgroup), 16-byte items first: the {kappa, kappa C_LJ} table (intra, inter)
 // in the accumulator type; the staged draws of every walker; the C_LJ table; the x, y and z
 // coordinate mirrors of every walker (stride pos_stride); ln W at the bin edges of every system
-// of the workgroup (system i at lds_off[i] + i); the 32-bit histograms (system i at lds_off[i]);
-// the staged bead indices of every walker; the bead descriptors of every system.
+// of the workgroup (system i at lds_off[i] + i); the staged bead indices and descriptors of every
+// walker; the 32-bit histograms (system i at lds_off[i]); the bead descriptors of every system.
 template <bool FP64, int SLOTS, bool PERIODIC>
 __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_sweeps, int pos_stride) {
     using A = AccP<FP64>;
@@ -513,9 +506,9 @@ __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_swe
     double *py = px + (size_t)n_wl * pos_stride;
     double *pz = py + (size_t)n_wl * pos_stride;
     double *lw = pz + (size_t)n_wl * pos_stride;
-    unsigned int *hist = reinterpret_cast<unsigned int *>(lw + bins_total + ns);
-    int *sb = reinterpret_cast<int *>(hist + bins_total);
-    int *binfo = sb + n_wl * kStage;
+    int2 *sb = reinterpret_cast<int2 *>(lw + bins_total + ns);
+    unsigned int *hist = reinterpret_cast<unsigned int *>(sb + n_wl * kStage);
+    int *binfo = reinterpret_cast<int *>(hist + bins_total);
     for (int i = 0; i < ns; ++i) {
         const SysDev &sd = a.sys[wi.sys[i]];
         const int off = wi.lds_off[i];
@@ -588,7 +581,7 @@ size_t sweep_pair_lds_bytes(long long bins_total, int n_sys, int n_waves, int po
     return 2 * sizeof(double2) * kMaxTypes * kMaxTypes + sizeof(Staged) * n_wl * kStage +
            sizeof(double) * kMaxTypes * kMaxTypes + 3 * sizeof(double) * n_wl * (size_t)pos_stride +
            sizeof(double) * (size_t)(bins_total + n_sys) + sizeof(unsigned int) * (size_t)bins_total +
-           sizeof(int) * n_wl * kStage + sizeof(int) * (size_t)n_sys * kMaxBeads;
+           sizeof(int2) * n_wl * kStage + sizeof(int) * (size_t)n_sys * kMaxBeads;
 }
 
 template <bool FP64, int SLOTS, bool PERIODIC>
