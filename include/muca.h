@@ -61,16 +61,16 @@ enum { MUCA_PREC_FP64 = 0, MUCA_PREC_FP32_SPLIT = 1 };
  * precision: MUCA_PREC_FP64 evaluates everything in FP64; MUCA_PREC_FP32_SPLIT evaluates pair
  * terms in FP32 and keeps coordinates, the running energy, ln W and the recursion in FP64.
  * resync_sweeps > 0 recomputes every walker's energy in FP64 every resync_sweeps sweeps.
- * waves_per_block: wavefronts per workgroup (0 = library default); walkers_per_wave: 1 runs
- * one walker per 64-lane wavefront, 2 runs two walkers of a system in the two 32-lane halves of
- * a wavefront (needs an even walkers_per_system and at most 8 waves per block), 0 lets the
- * library choose (2 when possible).  Two walkers per wave read ln W from its values at the bin
- * edges, which needs continuous weights (the two lines of Eq. 8 meeting at every inner bin edge
- * agree there, as the weight recursion maintains); weights set through muca_set_weights or
- * muca_set_state that are not switch the context to one walker per wave until continuous ones
- * are set again.  Neither setting changes any result: every walker's trajectory depends only on
- * its seed and walker index.  stream: a hipStream_t to run on, or NULL for a
- * stream created and owned by the context.
+ * waves_per_block: wavefronts per workgroup (0 = library default).  walkers_per_wave: 1 runs
+ * one walker per 64-lane wavefront; 2 or 4 run that many walkers of a system in 32- or 16-lane
+ * groups of a wavefront (walkers_per_system a multiple of it, at most 8 waves per block; 4 also
+ * needs at most 64 beads per system); 0 lets the library choose (2 when possible).  Several
+ * walkers per wave read ln W from its values at the bin edges, which needs continuous weights
+ * (the two lines of Eq. 8 meeting at every inner bin edge agree there, as the weight recursion
+ * maintains); weights set through muca_set_weights or muca_set_state that are not switch the
+ * context to one walker per wave until continuous ones are set again.  None of these settings
+ * changes any result: every walker's trajectory depends only on its seed and walker index.
+ * stream: a hipStream_t to run on, or NULL for a stream created and owned by the context.
  */
 typedef struct {
     int32_t n_systems;
@@ -100,7 +100,7 @@ typedef struct {
 
 /* Launch plan of the sweep (muca_get_launch_info). */
 typedef struct {
-    int32_t walkers_per_wave;   /* 1 or 2 */
+    int32_t walkers_per_wave;   /* 1, 2 or 4 */
     int32_t waves_per_block;
     int32_t paired;             /* 1: workgroups mix a long and a short system */
     int32_t workgroups;         /* workgroups per sweep launch */
@@ -185,9 +185,9 @@ int muca_get_accept_log(muca_ctx *ctx, int32_t sys, uint8_t *out, int64_t n_move
 int muca_get_state(muca_ctx *ctx, void *buf, size_t *bytes);
 int muca_set_state(muca_ctx *ctx, const void *buf, size_t bytes);
 
-/* Time the candidate sweep launches (one or two walkers per wave; 16, 8, 4, 2 or 1 waves per
- * workgroup; with several systems, with and without pairing long and short chains in one
- * workgroup) on probe_sweeps sweeps, keep the fastest and restore the sampling state, so
+/* Time the candidate sweep launches (one, two or four walkers per wave; 16, 8, 4, 2 or 1
+ * waves per workgroup; with several systems, with and without pairing long and short chains in
+ * one workgroup) on probe_sweeps sweeps, keep the fastest and restore the sampling state, so
  * results do not depend on tuning (every walker's trajectory is independent of the schedule).
  * Candidates whose LDS does not fit are skipped.  *chosen (host, may be NULL) receives the waves
  * per workgroup, negated for an unpaired schedule; muca_get_launch_info gives the full plan. */

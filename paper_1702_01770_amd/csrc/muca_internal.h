@@ -12,11 +12,13 @@ namespace muca {
 // Sweep kernels (muca_sweep.hip).
 hipError_t launch_sweep(const SweepArgs &a, bool fp64, int slots, bool periodic, int n_items,
                         int waves_per_block, size_t lds_bytes, long long n_sweeps, hipStream_t st);
-// Two walkers per wavefront (muca_sweep_pair.hip); pos_stride = LDS coordinate stride per walker.
-hipError_t launch_sweep_pair(const SweepArgs &a, bool fp64, int slots, bool periodic, int n_items,
-                             int waves_per_block, size_t lds_bytes, long long n_sweeps,
+// Several walkers per wavefront (muca_sweep_pair.hip): group = lanes per walker (32 or 16),
+// slots = bead slots per lane, pos_stride = LDS coordinate stride per walker.
+hipError_t launch_sweep_pair(const SweepArgs &a, bool fp64, int group, int slots, bool periodic,
+                             int n_items, int waves_per_block, size_t lds_bytes, long long n_sweeps,
                              int pos_stride, hipStream_t st);
-size_t sweep_pair_lds_bytes(long long bins_total, int n_sys, int n_waves, int pos_stride);
+size_t sweep_pair_lds_bytes(long long bins_total, int n_sys, int n_waves, int pos_stride,
+                            int group);
 hipError_t launch_walker_energy(const SweepArgs &a, int slots, bool periodic, int n_walkers,
                                 const int *walker_sys, hipStream_t st);
 

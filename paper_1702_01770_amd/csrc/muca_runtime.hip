@@ -56,9 +56,8 @@ struct muca_ctx {
     IterStatsDev *d_stats = nullptr;
     int stats_cap = 4096;
     int wpb = 16, n_items = 0;
-    int pack = 1;              // walkers per wave: 1 (k_sweep) or 2 (k_sweep_pair)
+    int pack = 1;              // walkers per wave: 1 (k_sweep), 2 or 4 (k_sweep_pair)
     int pos_stride = 0;        // LDS coordinate stride of k_sweep_pair
-    int pair_slots = 1;        // bead slots per lane of k_sweep_pair (32 lanes per walker)
     bool weights_continuous = true;   // ln W continuous at every bin edge (k_sweep_pair needs it)
     bool pack_fallback = false;       // one walker per wave because of discontinuous weights
     bool paired = true;
@@ -121,7 +120,16 @@ static size_t lds_for_bins(long long bins) {
 
 // LDS of one workgroup holding n_sys systems with `bins` bins in total.
 static size_t lds_need(const muca_ctx *ctx, long long bins, int n_sys, int wpb, int pack) {
-    return pack == 2 ? sweep_pair_lds_bytes(bins, n_sys, wpb, ctx->pos_stride) : lds_for_bins(bins);
+    return pack > 1 ? sweep_pair_lds_bytes(bins, n_sys, wpb, ctx->pos_stride, 64 / pack)
+                    : lds_for_bins(bins);
+}
+
+// Walkers per wave the context can use: 4 needs a multiple of 4 walkers per system and at most
+// 64 beads (four slots of 16 lanes), 2 an even number of walkers; both need continuous weights.
+static bool pack_ok(const muca_ctx *ctx, int pack) {
+    if (pack == 1) return true;
+    if (!ctx->weights_continuous || ctx->W % pack != 0) return false;
+    return pack == 2 || (pack == 4 && ctx->max_beads <= 64);
 }
 
 // Workgroup schedule.  A workgroup runs wpb waves of `pack` walkers each (consecutive walkers of
@@ -228,7 +236,7 @@ static int refresh_continuity(muca_ctx *ctx) {
         }
     }
     ctx->weights_continuous = ok;
-    if (!ok && ctx->pack == 2) {
+    if (!ok && ctx->pack > 1) {
         const int rc = build_schedule(ctx, std::min(16, ctx->W), true, 1);
         if (rc != MUCA_OK) return rc;
         ctx->pack_fallback = true;
@@ -244,9 +252,12 @@ static int launch_chunked(muca_ctx *ctx, long long n_sweeps) {
     long long left = n_sweeps;
     while (left > 0) {
         const long long c = std::min<long long>(left, ctx->chunk_sweeps);
-        if (ctx->pack == 2)
-            CK(launch_sweep_pair(ctx->args, ctx->fp64, ctx->pair_slots, ctx->periodic, ctx->n_items,
-                                 ctx->wpb, ctx->lds_bytes, c, ctx->pos_stride, ctx->stream));
+        if (ctx->pack > 1) {
+            const int group = 64 / ctx->pack;
+            CK(launch_sweep_pair(ctx->args, ctx->fp64, group, (ctx->max_beads + group - 1) / group,
+                                 ctx->periodic, ctx->n_items, ctx->wpb, ctx->lds_bytes, c,
+                                 ctx->pos_stride, ctx->stream));
+        }
         else
             CK(launch_sweep(ctx->args, ctx->fp64, ctx->slots, ctx->periodic, ctx->n_items, ctx->wpb,
                             ctx->lds_bytes, c, ctx->stream));
@@ -336,9 +347,10 @@ static int validate(const muca_config *c, std::string &why) {
     if (c->precision != MUCA_PREC_FP64 && c->precision != MUCA_PREC_FP32_SPLIT) { why = "bad precision"; return MUCA_E_INVAL; }
     if (c->resync_sweeps < 0 || c->rigid_per_sweep < 0) { why = "negative resync/rigid count"; return MUCA_E_INVAL; }
     if (c->waves_per_block < 0 || c->waves_per_block > 16) { why = "waves_per_block must be 0..16"; return MUCA_E_INVAL; }
-    if (c->walkers_per_wave < 0 || c->walkers_per_wave > 2) { why = "walkers_per_wave must be 0, 1 or 2"; return MUCA_E_INVAL; }
-    if (c->walkers_per_wave == 2 && (c->walkers_per_system % 2) != 0) { why = "walkers_per_wave = 2 needs an even walkers_per_system"; return MUCA_E_INVAL; }
-    if (c->walkers_per_wave == 2 && c->waves_per_block > 8) { why = "walkers_per_wave = 2 allows at most 8 waves per block"; return MUCA_E_INVAL; }
+    if (c->walkers_per_wave != 0 && c->walkers_per_wave != 1 && c->walkers_per_wave != 2 &&
+        c->walkers_per_wave != 4) { why = "walkers_per_wave must be 0, 1, 2 or 4"; return MUCA_E_INVAL; }
+    if (c->walkers_per_wave > 1 && (c->walkers_per_system % c->walkers_per_wave) != 0) { why = "walkers_per_system must be a multiple of walkers_per_wave"; return MUCA_E_INVAL; }
+    if (c->walkers_per_wave > 1 && c->waves_per_block > 8) { why = "more than one walker per wave allows at most 8 waves per block"; return MUCA_E_INVAL; }
     return MUCA_OK;
 }
 
@@ -404,7 +416,6 @@ int muca_init(const muca_config *cfg, muca_ctx **out) {
     ctx->total_bins = bin_off;
     ctx->slots = ctx->max_beads > 64 ? 2 : 1;
     ctx->npad = 64 * ctx->slots;
-    ctx->pair_slots = (ctx->max_beads + 31) / 32;
     ctx->pos_stride = (ctx->max_beads + 1) & ~1;
     ctx->lds_bytes = (size_t)ctx->max_bins * (sizeof(double) * 2 + sizeof(unsigned int)) +
                      sizeof(double) * kMaxTypes * kMaxTypes;
@@ -560,11 +571,15 @@ int muca_init(const muca_config *cfg, muca_ctx **out) {
     ctx->lds_limit = (size_t)dev_lds;
     // default: two walkers per wave when the walkers pair up, 8 such waves per workgroup
     int pack = cfg->walkers_per_wave > 0 ? cfg->walkers_per_wave : (ctx->W % 2 == 0 ? 2 : 1);
+    if (cfg->walkers_per_wave == 4 && ctx->max_beads > 64) {
+        ctx->err = "four walkers per wave need at most 64 beads per system";
+        return bail(MUCA_E_INVAL);
+    }
     if (cfg->walkers_per_wave == 0 && cfg->waves_per_block > 8) pack = 1;
     int wpb = cfg->waves_per_block > 0 ? cfg->waves_per_block : (pack == 2 ? 8 : 16);
     wpb = std::max(1, std::min(wpb, ctx->W / pack));
     rc = build_schedule(ctx, wpb, true, pack);
-    if (rc != MUCA_OK && cfg->walkers_per_wave == 0 && pack == 2) {
+    if (rc != MUCA_OK && cfg->walkers_per_wave == 0 && pack > 1) {
         pack = 1;      // the coordinate mirror does not fit beside the tables: one walker per wave
         wpb = std::min(cfg->waves_per_block > 0 ? cfg->waves_per_block : 16, ctx->W);
         rc = build_schedule(ctx, wpb, true, pack);
@@ -942,11 +957,11 @@ int muca_autotune(muca_ctx *ctx, int64_t probe_sweeps, int32_t *chosen) {
     if (rc != MUCA_OK) return rc;
     struct Cand { int pack, wpb; bool pair; };
     std::vector<Cand> cands;
-    for (int pack = 2; pack >= 1; --pack) {
-        if (pack == 2 && (ctx->W % 2 != 0 || !ctx->weights_continuous)) continue;
+    for (int pack : {4, 2, 1}) {
+        if (!pack_ok(ctx, pack)) continue;
         for (int pr = 1; pr >= 0; --pr)
             for (int c : {16, 8, 4, 2, 1}) {
-                if (pack == 2 && c > 8) continue;
+                if (pack > 1 && c > 8) continue;
                 if (c * pack > ctx->W) continue;
                 if (!pr && (ctx->n_sys == 1 || c < 8)) continue;   // pairing makes no difference
                 cands.push_back(Cand{pack, c, pr != 0});

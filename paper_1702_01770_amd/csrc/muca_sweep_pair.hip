@@ -1,13 +1,12 @@
-// Multicanonical Metropolis sweep, two walkers per wavefront (CDNA4, gfx950).
+// Multicanonical Metropolis sweep, several walkers per wavefront (CDNA4, gfx950).
 //
-// Same algorithm and random streams as k_sweep (muca_sweep.hip); this variant packs two walkers
-// of one system into a wave: lanes 0-31 run the first, lanes 32-63 the second, so the serial
-// part of a trial move (proposal, acceptance test, bookkeeping) is shared by two Markov chains
-// instead of one.  Bead j of a walker lives in lane (j mod 32) of its half, slot j / 32.
-// Values that are uniform within a half (bead index, energy, bin, ...) are plain VGPRs.
-// Coordinates are mirrored in LDS so that each half can read "its" moved bead and neighbours
-// with ordinary LDS loads; every update of a bead is written by all 32 lanes of its half, so a
-// lane never reads an LDS word that it has not written itself after the initial barrier.
+// Same algorithm and random streams as k_sweep (muca_sweep.hip); this variant packs 64 / G
+// walkers of one system into a wave, G = 32 or 16 lanes each (a group), so the serial part of a
+// trial move (proposal, acceptance test, bookkeeping) is shared by two or four Markov chains.
+// Bead j of a walker lives in lane (j mod G) of its group, slot j / G.  Values that are uniform
+// within a group (bead index, energy, bin, ...) are plain VGPRs.  Coordinates are mirrored in
+// LDS so that each group can read "its" moved bead and neighbours with ordinary LDS loads; every
+// update of a bead is written by all lanes of its group.
 // ln W (Eq. 8) is continuous and linear inside each bin, so LDS holds its values at the K + 1 bin
 // edges (8 bytes per bin) and a move reads the two edges of its bin with one ds_read2; the
 // runtime uses this kernel only for weights that are continuous (the Berg recursion keeps them
@@ -23,7 +22,6 @@ namespace muca {
 
 namespace {
 
-constexpr int kG = 32;   // lanes per walker
 
 template <bool FP64>
 using AccP = typename std::conditional<FP64, double, float>::type;
@@ -80,8 +78,32 @@ __device__ __forceinline__ double half_sum_f(float v) {
     v += dpp_f<0x140>(v);
     return row_pair_sum((double)v);
 }
-__device__ __forceinline__ double half_sum(double v) { return half_sum_d(v); }
-__device__ __forceinline__ double half_sum(float v) { return half_sum_f(v); }
+// Sum over the G lanes of each group, returned to every lane of the group: for G = 16 the DPP
+// row butterfly alone, for G = 32 followed by the row swap.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+    if constexpr (G == 32) {
+        return half_sum_d(v);
+    } else {
+        v += dpp_d<0xB1>(v);
+        v += dpp_d<0x4E>(v);
+        v += dpp_d<0x141>(v);
+        v += dpp_d<0x140>(v);
+        return v;
+    }
+}
+template <int G>
+__device__ __forceinline__ double group_sum(float v) {
+    if constexpr (G == 32) {
+        return half_sum_f(v);
+    } else {
+        v += dpp_f<0xB1>(v);
+        v += dpp_f<0x4E>(v);
+        v += dpp_f<0x141>(v);
+        v += dpp_f<0x140>(v);
+        return (double)v;
+    }
+}
 
 // ln W at t = (E - E_lo) / eps in bin k (t in [k, k+1) except at a tolerated window edge, where
 // the bin's line is extended), from the edge values le[k], le[k+1]
@@ -103,16 +125,16 @@ struct PairLds {
     double *x, *y, *z;         // this walker's coordinates
     const double *ctab;        // C_LJ[t][u], t, u < kMaxTypes
     const void *kc;            // {kappa, kappa C_LJ}[intra / inter][t][u] in the accumulator type
-    int2 *sb;                  // staged bead index and descriptor of the next kG moves (+1 spare)
-    Staged *sq;                // staged random values of the next kG moves (+1 spare)
+    int2 *sb;                  // staged bead index and descriptor of the next G moves (+1 spare)
+    Staged *sq;                // staged random values of the next G moves (+1 spare)
 };
 
-// Full FP64 energy of the walker of this half, from the LDS copy of its coordinates.
-template <int SLOTS, bool PERIODIC>
+// Full FP64 energy of the walker of this group, from the LDS copy of its coordinates.
+template <int G, int SLOTS, bool PERIODIC>
 __device__ double full_energy_pair(const SweepArgs &a, int N, const PairLds &L,
                                    const double (&px)[SLOTS], const double (&py)[SLOTS],
                                    const double (&pz)[SLOTS], const int (&inf)[SLOTS]) {
-    const int gl = threadIdx.x & 31;
+    const int gl = threadIdx.x & (G - 1);
     double acc = 0.0;
     for (int i = 0; i < N; ++i) {
         const double xi = L.x[i], yi = L.y[i], zi = L.z[i];
@@ -120,7 +142,7 @@ __device__ double full_energy_pair(const SweepArgs &a, int N, const PairLds &L,
         const int ci = bi_chain(infi), ti = bi_type(infi);
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
-            const int j = gl + kG * s;
+            const int j = gl + G * s;
             if (j < N && j > i) {
                 const bool same = bi_chain(inf[s]) == ci;
                 if (!(same && j == i + 1)) {
@@ -142,7 +164,7 @@ __device__ double full_energy_pair(const SweepArgs &a, int N, const PairLds &L,
     }
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-        const int j = gl + kG * s;
+        const int j = gl + G * s;
         if (j + 2 < N && !bi_last(inf[s]) && !bi_last(L.binfo[j + 1])) {
             double b0[3] = {L.x[j + 1] - px[s], L.y[j + 1] - py[s], L.z[j + 1] - pz[s]};
             double b1[3] = {L.x[j + 2] - L.x[j + 1], L.y[j + 2] - L.y[j + 1], L.z[j + 2] - L.z[j + 1]};
@@ -160,16 +182,16 @@ __device__ double full_energy_pair(const SweepArgs &a, int N, const PairLds &L,
             }
         }
     }
-    return half_sum(acc);
+    return group_sum<G>(acc);
 }
 
-template <bool FP64, int SLOTS, bool PERIODIC>
+template <bool FP64, int G, int SLOTS, bool PERIODIC>
 __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const PairLds &L,
                          long long n_sweeps) {
     using A = AccP<FP64>;
     using A2 = typename std::conditional<FP64, double2, float2>::type;
-    const int lane = threadIdx.x & 63, gl = lane & 31;
-    // both halves of the wave sample the same system: these are wave-uniform
+    const int lane = threadIdx.x & 63, gl = lane & (G - 1);
+    // all groups of the wave sample the same system: these are wave-uniform
     const int N = __builtin_amdgcn_readfirstlane(sd.n_beads);
     const int M = __builtin_amdgcn_readfirstlane(sd.n_chains);
     const int K = __builtin_amdgcn_readfirstlane(sd.n_bins);
@@ -185,7 +207,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
     int inf[SLOTS], chn[SLOTS], trow[SLOTS];
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-        const int j = gl + kG * s;
+        const int j = gl + G * s;
         const bool alive = j < N;
         px[s] = alive ? P[j] : 0.0;
         py[s] = alive ? P[npad + j] : 0.0;
@@ -222,8 +244,8 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
     unsigned int *alog = a.acc_log ? a.acc_log + (size_t)w * a.acc_log_words : nullptr;
 
     while (done < total) {
-        // ---- each half draws the next (up to) 32 moves of its walker, one per lane ----
-        const int nblk = (int)min((long long)kG, total - done);
+        // ---- each group draws the next (up to) G moves of its walker, one per lane ----
+        const int nblk = (int)min((long long)G, total - done);
         {
             const int idx = m + gl;
             const unsigned long long Sl = S + (unsigned long long)(idx / N);
@@ -248,7 +270,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             q.lnu = log(u3);
             L.sb[gl] = make_int2(blane, binf_l);
             L.sq[gl] = q;
-            if (gl == 0) L.sb[kG] = make_int2(0, L.binfo[0]);   // spare entry for the last prefetch
+            if (gl == 0) L.sb[G] = make_int2(0, L.binfo[0]);    // spare entry for the last prefetch
             __builtin_amdgcn_wave_barrier();
         }
         int2 bi_nx = L.sb[0];
@@ -302,8 +324,8 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             A acc = 0;
 #pragma unroll
             for (int s = 0; s < SLOTS; ++s) {
-                if (s > 0 && kG * s >= N) break;         // wave-uniform: no bead in this slot
-                const int j = gl + kG * s;
+                if (s > 0 && G * s >= N) break;          // wave-uniform: no bead in this slot
+                const int j = gl + G * s;
                 const int d = j - b;
                 const bool same = chn[s] == cb;
                 // skip the moved bead itself (d = 0, same chain), its bonded neighbours and empty
@@ -341,7 +363,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 coef = same ? coef : (A)0;
                 acc += coef * (ux[s] * mxa + uy[s] * mya + uz[s] * mza);
             }
-            const double dE = half_sum(acc);
+            const double dE = group_sum<G>(acc);
             const double En = E + dE;
             const double t = (En - e_lo) * inv_eps;
             const bool inwin = (t >= 0.0) && (t < (double)K);
@@ -358,7 +380,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 const A bpx = (A)(xpx - nx), bpy = (A)(xpy - ny), bpz = (A)(xpz - nz);
 #pragma unroll
                 for (int s = 0; s < SLOTS; ++s) {
-                    const int j = gl + kG * s;
+                    const int j = gl + G * s;
                     const bool lo_b = (j == b - 1) && !fst, at_b = (j == b) && !lst;
                     ux[s] = lo_b ? bmx : (at_b ? bpx : ux[s]);
                     uy[s] = lo_b ? bmy : (at_b ? bpy : uy[s]);
@@ -394,7 +416,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                             const int ti = bi_type(L.binfo[ib]);
 #pragma unroll
                             for (int s = 0; s < SLOTS; ++s) {
-                                const int j = gl + kG * s;
+                                const int j = gl + G * s;
                                 if (j < N && chn[s] != ch) {
                                     double dxo = xi - px[s], dyo = yi - py[s], dzo = zi - pz[s];
                                     double dxn = xs - px[s], dyn = ys - py[s], dzn = zs - pz[s];
@@ -411,7 +433,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                                 }
                             }
                         }
-                        const double rdE = half_sum(racc);
+                        const double rdE = group_sum<G>(racc);
                         const double rEn = E + rdE;
                         const double rt = (rEn - e_lo) * inv_eps;
                         const bool rin = (rt >= 0.0) && (rt < (double)K);
@@ -440,7 +462,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 }
                 ++S;
                 if (a.resync_sweeps > 0 && (S % (unsigned long long)a.resync_sweeps) == 0) {
-                    const double Ef = full_energy_pair<SLOTS, PERIODIC>(a, N, L, px, py, pz, inf);
+                    const double Ef = full_energy_pair<G, SLOTS, PERIODIC>(a, N, L, px, py, pz, inf);
                     const double dr = fabs(Ef - E);
                     max_drift = fmax(max_drift, dr);
                     if (dr > a.drift_tol && gl == 0) set_error(a.err, -5);
@@ -465,7 +487,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
 
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-        const int j = gl + kG * s;
+        const int j = gl + G * s;
         if (j < N) { P[j] = px[s]; P[npad + j] = py[s]; P[2 * npad + j] = pz[s]; }
     }
     if (gl == 0) {
@@ -482,22 +504,23 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
 
 }  // namespace
 
-constexpr int kStage = kG + 1;   // staged moves per walker (+1 spare for the prefetch)
 
 // LDS layout (per workgroup), 16-byte items first: the {kappa, kappa C_LJ} table (intra, inter)
 // in the accumulator type; the staged draws of every walker; the C_LJ table; the x, y and z
 // coordinate mirrors of every walker (stride pos_stride); ln W at the bin edges of every system
 // of the workgroup (system i at lds_off[i] + i); the staged bead indices and descriptors of every
 // walker; the 32-bit histograms (system i at lds_off[i]); the bead descriptors of every system.
-template <bool FP64, int SLOTS, bool PERIODIC>
+template <bool FP64, int G, int SLOTS, bool PERIODIC>
 __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_sweeps, int pos_stride) {
+    constexpr int kStage = G + 1;   // staged moves per walker (+1 spare for the prefetch)
+    constexpr int kPer = 64 / G;    // walkers per wave
     using A = AccP<FP64>;
     using A2 = typename std::conditional<FP64, double2, float2>::type;
     extern __shared__ double2 lds_p[];
     const WorkItem &wi = a.work[blockIdx.x];
     const int ns = wi.n_sys;
     const int n_waves = blockDim.x >> 6;
-    const int n_wl = 2 * n_waves;
+    const int n_wl = kPer * n_waves;
     const int bins_total = wi.lds_off[ns - 1] + a.sys[wi.sys[ns - 1]].n_bins;
     A2 *kc = reinterpret_cast<A2 *>(lds_p);
     Staged *sq = reinterpret_cast<Staged *>(lds_p + 2 * kMaxTypes * kMaxTypes);
@@ -535,13 +558,13 @@ __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_swe
         kc[threadIdx.x] = v;
     }
     const int wave = threadIdx.x >> 6;
-    const bool hi = (threadIdx.x & 63) >= 32;
+    const int grp = (threadIdx.x & 63) / G;
     const int w0 = wi.walker[wave];
-    const int wl = 2 * wave + (hi ? 1 : 0);
+    const int wl = kPer * wave + grp;
     if (w0 >= 0) {                  // coordinate mirror of this half's walker
         const int N = a.sys[wi.sys[wi.slot[wave]]].n_beads;
-        const double *P = a.pos + (size_t)(w0 + (hi ? 1 : 0)) * 3 * a.npad;
-        for (int j = threadIdx.x & 31; j < N; j += kG) {
+        const double *P = a.pos + (size_t)(w0 + grp) * 3 * a.npad;
+        for (int j = threadIdx.x & (G - 1); j < N; j += G) {
             px[(size_t)wl * pos_stride + j] = P[j];
             py[(size_t)wl * pos_stride + j] = P[a.npad + j];
             pz[(size_t)wl * pos_stride + j] = P[2 * a.npad + j];
@@ -563,7 +586,7 @@ __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_swe
         L.kc = kc;
         L.sb = sb + wl * kStage;
         L.sq = sq + (size_t)wl * kStage;
-        run_pair<FP64, SLOTS, PERIODIC>(a, sd, w0 + (hi ? 1 : 0), L, n_sweeps);
+        run_pair<FP64, G, SLOTS, PERIODIC>(a, sd, w0 + grp, L, n_sweeps);
     }
     __syncthreads();
     for (int i = 0; i < ns; ++i) {
@@ -576,19 +599,21 @@ __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_swe
     }
 }
 
-size_t sweep_pair_lds_bytes(long long bins_total, int n_sys, int n_waves, int pos_stride) {
-    const size_t n_wl = 2 * (size_t)n_waves;
-    return 2 * sizeof(double2) * kMaxTypes * kMaxTypes + sizeof(Staged) * n_wl * kStage +
+size_t sweep_pair_lds_bytes(long long bins_total, int n_sys, int n_waves, int pos_stride,
+                            int group) {
+    const size_t n_wl = (size_t)(64 / group) * n_waves;
+    const size_t stage = (size_t)group + 1;
+    return 2 * sizeof(double2) * kMaxTypes * kMaxTypes + sizeof(Staged) * n_wl * stage +
            sizeof(double) * kMaxTypes * kMaxTypes + 3 * sizeof(double) * n_wl * (size_t)pos_stride +
            sizeof(double) * (size_t)(bins_total + n_sys) + sizeof(unsigned int) * (size_t)bins_total +
-           sizeof(int2) * n_wl * kStage + sizeof(int) * (size_t)n_sys * kMaxBeads;
+           sizeof(int2) * n_wl * stage + sizeof(int) * (size_t)n_sys * kMaxBeads;
 }
 
-template <bool FP64, int SLOTS, bool PERIODIC>
+template <bool FP64, int G, int SLOTS, bool PERIODIC>
 static hipError_t launch_pair_t(const SweepArgs &a, int n_items, int waves, size_t lds,
                                 long long n_sweeps, int pos_stride, hipStream_t st) {
     if (waves < 1 || waves > 8 || pos_stride < 1) return hipErrorInvalidValue;   // __launch_bounds__(512)
-    auto kern = k_sweep_pair<FP64, SLOTS, PERIODIC>;
+    auto kern = k_sweep_pair<FP64, G, SLOTS, PERIODIC>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -596,25 +621,36 @@ static hipError_t launch_pair_t(const SweepArgs &a, int n_items, int waves, size
     return hipGetLastError();
 }
 
-template <bool FP64, bool PERIODIC>
+template <bool FP64, bool PERIODIC, int G>
 static hipError_t launch_pair_s(const SweepArgs &a, int slots, int n_items, int waves, size_t lds,
                                 long long n_sweeps, int pos_stride, hipStream_t st) {
     switch (slots) {
-        case 1: return launch_pair_t<FP64, 1, PERIODIC>(a, n_items, waves, lds, n_sweeps, pos_stride, st);
-        case 2: return launch_pair_t<FP64, 2, PERIODIC>(a, n_items, waves, lds, n_sweeps, pos_stride, st);
-        case 3: return launch_pair_t<FP64, 3, PERIODIC>(a, n_items, waves, lds, n_sweeps, pos_stride, st);
-        default: return launch_pair_t<FP64, 4, PERIODIC>(a, n_items, waves, lds, n_sweeps, pos_stride, st);
+        case 1: return launch_pair_t<FP64, G, 1, PERIODIC>(a, n_items, waves, lds, n_sweeps, pos_stride, st);
+        case 2: return launch_pair_t<FP64, G, 2, PERIODIC>(a, n_items, waves, lds, n_sweeps, pos_stride, st);
+        case 3: return launch_pair_t<FP64, G, 3, PERIODIC>(a, n_items, waves, lds, n_sweeps, pos_stride, st);
+        case 4: return launch_pair_t<FP64, G, 4, PERIODIC>(a, n_items, waves, lds, n_sweeps, pos_stride, st);
+        default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_sweep_pair(const SweepArgs &a, bool fp64, int slots, bool periodic, int n_items,
-                             int waves, size_t lds, long long n_sweeps, int pos_stride,
+template <bool FP64, bool PERIODIC>
+static hipError_t launch_pair_g(const SweepArgs &a, int group, int slots, int n_items, int waves,
+                                size_t lds, long long n_sweeps, int pos_stride, hipStream_t st) {
+    if (group == 16)
+        return launch_pair_s<FP64, PERIODIC, 16>(a, slots, n_items, waves, lds, n_sweeps, pos_stride, st);
+    if (group == 32)
+        return launch_pair_s<FP64, PERIODIC, 32>(a, slots, n_items, waves, lds, n_sweeps, pos_stride, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep_pair(const SweepArgs &a, bool fp64, int group, int slots, bool periodic,
+                             int n_items, int waves, size_t lds, long long n_sweeps, int pos_stride,
                              hipStream_t st) {
     if (fp64)
-        return periodic ? launch_pair_s<true, true>(a, slots, n_items, waves, lds, n_sweeps, pos_stride, st)
-                        : launch_pair_s<true, false>(a, slots, n_items, waves, lds, n_sweeps, pos_stride, st);
-    return periodic ? launch_pair_s<false, true>(a, slots, n_items, waves, lds, n_sweeps, pos_stride, st)
-                    : launch_pair_s<false, false>(a, slots, n_items, waves, lds, n_sweeps, pos_stride, st);
+        return periodic ? launch_pair_g<true, true>(a, group, slots, n_items, waves, lds, n_sweeps, pos_stride, st)
+                        : launch_pair_g<true, false>(a, group, slots, n_items, waves, lds, n_sweeps, pos_stride, st);
+    return periodic ? launch_pair_g<false, true>(a, group, slots, n_items, waves, lds, n_sweeps, pos_stride, st)
+                    : launch_pair_g<false, false>(a, group, slots, n_items, waves, lds, n_sweeps, pos_stride, st);
 }
 
 }  // namespace muca

@@ -73,45 +73,65 @@ def _compare(lib, orc, wl, walkers, n_sweeps, weights_by_sys=None, log_moves=Non
     m.close()
 
 
-# pack = walkers per wavefront: 1 runs k_sweep, 2 runs k_sweep_pair (two 32-lane halves)
-@pytest.mark.parametrize("pack", [1, 2])
+def _walkers(pack, at_least):
+    """Smallest multiple of pack that is >= at_least."""
+    return -(-at_least // pack) * pack
+
+
+# pack = walkers per wavefront: 1 runs k_sweep; 2 and 4 run k_sweep_pair with groups of 32 and 16
+# lanes per walker
+@pytest.mark.parametrize("pack", [1, 2, 4])
 def test_fp64_single_chain_flat_weights(lib, orc, pack):
     wl = workloads.single_chain()
     _compare(lib, orc, wl, walkers=pack, n_sweeps=3000, pack=pack)
 
 
-@pytest.mark.parametrize("pack", [1, 2])
+@pytest.mark.parametrize("pack", [1, 2, 4])
 def test_fp64_single_chain_muca_weights_several_walkers(lib, orc, pack):
     wl = workloads.single_chain()
     res = orc.muca(wl, n_iter=4, n_sweeps=4000, walkers=2)
-    _compare(lib, orc, wl, walkers=6, n_sweeps=1500, weights_by_sys={0: res["weights"]},
-             pack=pack)
+    _compare(lib, orc, wl, walkers=_walkers(pack, 6), n_sweeps=1500,
+             weights_by_sys={0: res["weights"]}, pack=pack)
 
 
-@pytest.mark.parametrize("pack", [1, 2])
+@pytest.mark.parametrize("pack", [1, 2, 4])
 def test_fp64_batched_uneven_lengths(lib, orc, pack):
     wl = workloads.batched_chains(n_seq=3, n_min=13, n_max=60)
-    _compare(lib, orc, wl, walkers=2 + pack, n_sweeps=300, pack=pack)
+    _compare(lib, orc, wl, walkers=_walkers(pack, 3), n_sweeps=300, pack=pack)
 
 
-@pytest.mark.parametrize("pack", [1, 2])
+@pytest.mark.parametrize("pack", [1, 2, 4])
 def test_fp64_batched_paired_workgroups(lib, orc, pack):
     """Long and short systems sharing workgroups (8 waves: half run the longest remaining
     system, half the shortest), with a ragged last workgroup per system."""
     wl = workloads.batched_chains(n_seq=3, n_min=13, n_max=60)
-    _compare(lib, orc, wl, walkers=18, n_sweeps=60, pack=pack, waves_per_block=8)
+    _compare(lib, orc, wl, walkers=_walkers(pack, 18), n_sweeps=60, pack=pack,
+             waves_per_block=8)
 
 
-@pytest.mark.parametrize("pack", [1, 2])
+@pytest.mark.parametrize("pack", [1, 2, 4])
 def test_fp64_aggregation_periodic_rigid(lib, orc, pack):
     wl = workloads.aggregation()
-    _compare(lib, orc, wl, walkers=2 + pack, n_sweeps=400, pack=pack)
+    _compare(lib, orc, wl, walkers=_walkers(pack, 3), n_sweeps=400, pack=pack)
 
 
 @pytest.mark.parametrize("pack", [1, 2])
 def test_fp64_cross_seeding_two_slots_torsion(lib, orc, pack):
     wl = workloads.cross_seeding()
     _compare(lib, orc, wl, walkers=2, n_sweeps=200, pack=pack)
+
+
+def test_four_walkers_per_wave_limits(lib):
+    """Four walkers per wave hold at most 64 beads (four slots of 16 lanes) and need a multiple
+    of four walkers per system."""
+    wl = workloads.cross_seeding(walkers=4)                       # 76 beads
+    with pytest.raises(lib.MucaError) as ei:
+        lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers_per_wave=4)
+    assert "INVAL" in str(ei.value)
+    wl = workloads.single_chain()
+    with pytest.raises(lib.MucaError) as ei:
+        lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=6, walkers_per_wave=4)
+    assert "INVAL" in str(ei.value)
 
 
 def test_weight_update_matches_oracle(lib, orc):
@@ -238,7 +258,7 @@ def test_drift_detector_fires_on_corrupted_energy(lib):
     m.close()
 
 
-@pytest.mark.parametrize("pack", [1, 2])
+@pytest.mark.parametrize("pack", [1, 2, 4])
 def test_window_edge_tolerance(lib, pack):
     """A running energy up to 1e-3 outside the window (what FP32 accumulation can leave at an edge
     until the next FP64 resync) is kept in the edge bin; further outside it is an error."""
@@ -247,7 +267,7 @@ def test_window_edge_tolerance(lib, pack):
     sp = wl.systems[0]
     e_hi = sp.e_lo + sp.n_bins * wl.bin_width
     for offset, ok in ((5e-4, True), (1e-2, False)):
-        m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=2, precision=1,
+        m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=4, precision=1,
                                    resync_sweeps=10, walkers_per_wave=pack)
         blob = bytearray(m.get_state())
         hdr = struct.unpack_from("6Q", blob, 0)
