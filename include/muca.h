@@ -34,7 +34,7 @@ enum {
     MUCA_E_STATE = -6    /* call order or size mismatch */
 };
 
-enum { MUCA_BOX_NONE = 0, MUCA_BOX_PERIODIC = 2 };
+enum { MUCA_BOX_NONE = 0, MUCA_BOX_SPHERE = 1, MUCA_BOX_PERIODIC = 2 };
 enum { MUCA_PREC_FP64 = 0, MUCA_PREC_FP32_SPLIT = 1 };
 
 /*
@@ -50,8 +50,10 @@ enum { MUCA_PREC_FP64 = 0, MUCA_PREC_FP32_SPLIT = 1 };
  *   E = sum_chains [k_bend sum (1 - cos theta) + k_tors sum (1 - u_i.u_{i+2})
  *                   + k_lj_intra sum_{|i-j|>1} (r^-12 - C r^-6)]
  *       + k_lj_inter sum_{pairs on different chains} (r^-12 - C r^-6),
- *   C = c_lj[type_i * n_types + type_j] (symmetric, n_types <= 4); periodic boxes use the
- *   minimum image on every axis.
+ *   C = c_lj[type_i * n_types + type_j] (symmetric, n_types <= 4); periodic boxes (cube of
+ *   edge box_len) use the minimum image on every axis; the steric sphere (radius box_len about
+ *   the origin, the container of the paper's simulations) rejects every trial move that would
+ *   take a bead outside it, and every initial bead must lie inside it.
  * Energy window of system s: [e_lo[s], e_lo[s] + n_bins[s] * bin_width), bins of width
  * bin_width; ln W(E) = -beta_k E + alpha_k (Eq. 8), starting from W = 1.
  * Moves: one sweep = N single-bead trial moves (end bead: bond along d + cap_rho g with g

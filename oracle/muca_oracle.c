@@ -69,13 +69,21 @@ static void walker_key(uint64_t seed, uint32_t walker, uint32_t *k0, uint32_t *k
 /* System description and energy                                                              */
 /* ------------------------------------------------------------------------------------------ */
 typedef struct {
-    int32_t n_beads, n_chains, n_types, box_kind;  /* box_kind: 0 none, 2 periodic cube */
+    int32_t n_beads, n_chains, n_types, box_kind;  /* 0 none, 1 steric sphere, 2 periodic cube */
     const int32_t *chain_start;                     /* n_chains + 1 bead offsets */
     const uint8_t *type;                            /* n_beads letters, < n_types */
     const double *c_lj;                             /* n_types x n_types, Eq. (1) */
     double k_intra, k_inter, k_bend, k_tors;
-    double box_len;
+    double box_len;                                 /* cube edge, or sphere radius */
 } orc_system;
+
+/* Steric sphere of radius box_len about the origin (the container of the paper's simulations,
+ * Sec. 4): a bead may not leave it, so a trial move that would take one outside is rejected. */
+static int outside_sphere(const orc_system *s, const double *x)
+{
+    if (s->box_kind != 1) return 0;
+    return x[0] * x[0] + x[1] * x[1] + x[2] * x[2] > s->box_len * s->box_len;
+}
 
 typedef struct {
     double e_lo, bin_width;
@@ -334,6 +342,7 @@ int orc_run(const orc_system *s, const orc_weights *w, const orc_moves *mv, uint
             double e_new = e + (after - before);
             int64_t k_new;
             int acc = metropolis(w, e, k, e_new, u01(r[3]), &k_new);
+            if (outside_sphere(s, newpos)) acc = 0;
             if (acc) { e = e_new; k = k_new; cnt->accepted++; }
             else {
                 memcpy(xb, saved, sizeof saved);
@@ -367,6 +376,8 @@ int orc_run(const orc_system *s, const orc_weights *w, const orc_moves *mv, uint
                 double e_new = e + (after - before);
                 int64_t k_new;
                 int acc = metropolis(w, e, k, e_new, u01(r2[0]), &k_new);
+                for (int i = s->chain_start[ch]; i < s->chain_start[ch + 1]; ++i)
+                    if (outside_sphere(s, pos + 3 * i)) acc = 0;
                 if (acc) { e = e_new; k = k_new; cnt->rigid_accepted++; }
                 else {
                     memcpy(pos + 3 * c0, keep, sizeof(double) * 3 * (size_t)nc);

@@ -63,7 +63,8 @@ struct SweepArgs {
     double c_lj[kMaxTypes * kMaxTypes];
     int n_types;
     double k_intra, k_inter, k_bend, k_tors;
-    double box_len, inv_box;
+    double box_len, inv_box;    // periodic cube (0 otherwise)
+    double sphere_r2;           // squared radius of the steric sphere (0: no sphere)
     double bin_width, inv_bin;
     double crank_max, cap_rho, trans_max;
     int rigid_per_sweep;

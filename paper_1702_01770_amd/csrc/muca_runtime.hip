@@ -248,6 +248,17 @@ static int refresh_continuity(muca_ctx *ctx) {
     return MUCA_OK;
 }
 
+// True when every one of the n beads (host [n][3]) lies in the steric sphere (or there is none).
+static bool inside_sphere(const muca_ctx *ctx, const double *pos, size_t n) {
+    const double r2 = ctx->args.sphere_r2;
+    if (r2 <= 0.0) return true;
+    for (size_t i = 0; i < n; ++i) {
+        const double *x = pos + 3 * i;
+        if (x[0] * x[0] + x[1] * x[1] + x[2] * x[2] > r2) return false;
+    }
+    return true;
+}
+
 static int launch_chunked(muca_ctx *ctx, long long n_sweeps) {
     long long left = n_sweeps;
     while (left > 0) {
@@ -340,8 +351,8 @@ static int validate(const muca_config *c, std::string &why) {
     for (int i = 0; i < c->n_types; ++i)
         for (int j = 0; j < c->n_types; ++j)
             if (c->c_lj[i * c->n_types + j] != c->c_lj[j * c->n_types + i]) { why = "c_lj not symmetric"; return MUCA_E_INVAL; }
-    if (c->box_kind != MUCA_BOX_NONE && c->box_kind != MUCA_BOX_PERIODIC) { why = "unsupported box_kind"; return MUCA_E_INVAL; }
-    if (c->box_kind == MUCA_BOX_PERIODIC && !(c->box_len > 0.0)) { why = "periodic box needs box_len > 0"; return MUCA_E_INVAL; }
+    if (c->box_kind != MUCA_BOX_NONE && c->box_kind != MUCA_BOX_SPHERE && c->box_kind != MUCA_BOX_PERIODIC) { why = "unsupported box_kind"; return MUCA_E_INVAL; }
+    if (c->box_kind != MUCA_BOX_NONE && !(c->box_len > 0.0)) { why = "a box needs box_len > 0"; return MUCA_E_INVAL; }
     if (!(c->bin_width > 0.0)) { why = "bin_width must be > 0"; return MUCA_E_INVAL; }
     if (c->walkers_per_system < 1) { why = "walkers_per_system < 1"; return MUCA_E_INVAL; }
     if (c->precision != MUCA_PREC_FP64 && c->precision != MUCA_PREC_FP32_SPLIT) { why = "bad precision"; return MUCA_E_INVAL; }
@@ -401,6 +412,16 @@ int muca_init(const muca_config *cfg, muca_ctx **out) {
                 }
             }
             b0 += h.chain_len[c];
+        }
+        if (cfg->box_kind == MUCA_BOX_SPHERE) {
+            const double r2 = cfg->box_len * cfg->box_len;
+            for (int i = 0; i < h.n_beads; ++i) {
+                const double *x = h.init_pos.data() + 3 * i;
+                if (x[0] * x[0] + x[1] * x[1] + x[2] * x[2] > r2) {
+                    ctx->err = "an initial bead lies outside the steric sphere";
+                    return bail(MUCA_E_INVAL);
+                }
+            }
         }
         bead_idx += h.n_beads;
         h.n_bins = cfg->n_bins[s];
@@ -547,6 +568,7 @@ int muca_init(const muca_config *cfg, muca_ctx **out) {
     a.k_tors = cfg->k_tors;
     a.box_len = ctx->periodic ? cfg->box_len : 0.0;
     a.inv_box = ctx->periodic ? 1.0 / cfg->box_len : 0.0;
+    a.sphere_r2 = cfg->box_kind == MUCA_BOX_SPHERE ? cfg->box_len * cfg->box_len : 0.0;
     a.bin_width = cfg->bin_width;
     a.inv_bin = 1.0 / cfg->bin_width;
     a.crank_max = cfg->crank_max;
@@ -744,6 +766,8 @@ int muca_set_walkers(muca_ctx *ctx, int32_t sys, const double *pos, const uint64
     CK(hipStreamSynchronize(ctx->stream));
     const SysHost &h = ctx->sys[sys];
     const int W = ctx->W, npad = ctx->npad;
+    if (!inside_sphere(ctx, pos, (size_t)W * h.n_beads))
+        return fail(ctx, MUCA_E_INVAL, "a bead lies outside the steric sphere");
     std::vector<double> buf((size_t)W * 3 * npad, 0.0);
     for (int w = 0; w < W; ++w)
         for (int j = 0; j < h.n_beads; ++j)

@@ -295,8 +295,10 @@ __device__ void run_walker(const SweepArgs &a, const SysDev &sd, int sys, int w,
             const int kn = inwin ? (int)t : 0;
             const double2 wn = lnw[kn];
             const double lnw_new = -wn.x * En + wn.y;
+            // steric sphere: a bead may not leave it
+            const bool inside = a.sphere_r2 <= 0.0 || nx * nx + ny * ny + nz * nz <= a.sphere_r2;
             const int accept = __builtin_amdgcn_readfirstlane(
-                (inwin && (rl_d(lnu_l, i) < lnw_new - lnw_cur)) ? 1 : 0);
+                (inwin && inside && (rl_d(lnu_l, i) < lnw_new - lnw_cur)) ? 1 : 0);
             n_wrej += inwin ? 0u : 1u;
             if (alog && (long long)n_mv < a.acc_log_moves && accept && lane == 0)
                 atomicOr(&alog[n_mv >> 5], 1u << (n_mv & 31));
@@ -339,9 +341,12 @@ __device__ void run_walker(const SweepArgs &a, const SysDev &sd, int sys, int w,
                         const double lnu_r = log(u01(r2.x));
                         const int cs = sd.chain_start[ch], ce = sd.chain_start[ch + 1];
                         AccT<FP64> racc = 0;
+                        bool rinside = true;
                         for (int ib = cs; ib < ce; ++ib) {
                             const double xi = bc_d(px, ib), yi = bc_d(py, ib), zi = bc_d(pz, ib);
                             const double xs = xi + tx, ys = yi + ty, zs = zi + tz;
+                            if (a.sphere_r2 > 0.0 && xs * xs + ys * ys + zs * zs > a.sphere_r2)
+                                rinside = false;
                             const int ti = bi_type(bc_i(inf, ib));
 #pragma unroll
                             for (int s = 0; s < SLOTS; ++s) {
@@ -370,7 +375,7 @@ __device__ void run_walker(const SweepArgs &a, const SysDev &sd, int sys, int w,
                         const double2 rw = lnw[rkn];
                         const double rlnw = -rw.x * rEn + rw.y;
                         const int racc_ok = __builtin_amdgcn_readfirstlane(
-                            (rin && (lnu_r < rlnw - lnw_cur)) ? 1 : 0);
+                            (rin && rinside && (lnu_r < rlnw - lnw_cur)) ? 1 : 0);
                         n_wrej += rin ? 0u : 1u;
                         ++n_rig;
                         if (racc_ok) {

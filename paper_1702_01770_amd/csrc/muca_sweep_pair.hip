@@ -369,7 +369,9 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             const bool inwin = (t >= 0.0) && (t < (double)K);
             const int kn = inwin ? (int)t : 0;
             const double lnw_new = lnw_at(L.lw, kn, t);
-            const bool accept = inwin && (q.lnu < lnw_new - lnw_cur);
+            // steric sphere: a bead may not leave it
+            const bool inside = a.sphere_r2 <= 0.0 || nx * nx + ny * ny + nz * nz <= a.sphere_r2;
+            const bool accept = inwin && inside && (q.lnu < lnw_new - lnw_cur);
             n_wrej += inwin ? 0u : 1u;
             if (alog && (long long)n_mv < a.acc_log_moves && accept && gl == 0)
                 atomicOr(&alog[n_mv >> 5], 1u << (n_mv & 31));
@@ -410,9 +412,12 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                         const double lnu_r = log(u01(r2.x));
                         const int cs = sd.chain_start[ch], ce = sd.chain_start[ch + 1];
                         A racc = 0;
+                        bool rinside = true;
                         for (int ib = cs; ib < ce; ++ib) {
                             const double xi = L.x[ib], yi = L.y[ib], zi = L.z[ib];
                             const double xs = xi + tx, ys = yi + ty, zs = zi + tz;
+                            if (a.sphere_r2 > 0.0 && xs * xs + ys * ys + zs * zs > a.sphere_r2)
+                                rinside = false;
                             const int ti = bi_type(L.binfo[ib]);
 #pragma unroll
                             for (int s = 0; s < SLOTS; ++s) {
@@ -439,7 +444,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                         const bool rin = (rt >= 0.0) && (rt < (double)K);
                         const int rkn = rin ? (int)rt : 0;
                         const double rlnw = lnw_at(L.lw, rkn, rt);
-                        const bool rok = rin && (lnu_r < rlnw - lnw_cur);
+                        const bool rok = rin && rinside && (lnu_r < rlnw - lnw_cur);
                         n_wrej += rin ? 0u : 1u;
                         ++n_rig;
                         if (rok) {

@@ -121,6 +121,26 @@ def test_fp64_cross_seeding_two_slots_torsion(lib, orc, pack):
     _compare(lib, orc, wl, walkers=2, n_sweeps=200, pack=pack)
 
 
+@pytest.mark.parametrize("pack", [1, 2, 4])
+def test_fp64_steric_sphere(lib, orc, pack):
+    """The paper's container: two 9-bead chains in a sphere of radius 6 (rigid translations too)
+    and a 13-bead chain in a sphere of radius 6.5; moves leaving the sphere are rejected on both
+    sides, move for move."""
+    import dataclasses
+    wl = workloads.confined(radius=6.0)
+    _compare(lib, orc, wl, walkers=_walkers(pack, 3), n_sweeps=500, pack=pack)
+    wl = dataclasses.replace(workloads.single_chain(), box_kind=workloads.BOX_SPHERE, box_len=6.5)
+    _compare(lib, orc, wl, walkers=_walkers(pack, 2), n_sweeps=1500, pack=pack)
+
+
+def test_initial_bead_outside_sphere_is_rejected(lib):
+    import dataclasses
+    wl = dataclasses.replace(workloads.single_chain(), box_kind=workloads.BOX_SPHERE, box_len=5.0)
+    with pytest.raises(lib.MucaError) as ei:
+        lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=2)
+    assert "INVAL" in str(ei.value)
+
+
 def test_four_walkers_per_wave_limits(lib):
     """Four walkers per wave hold at most 64 beads (four slots of 16 lanes) and need a multiple
     of four walkers per system."""

@@ -30,7 +30,8 @@ TYPE_B = 1
 C_LJ_PAPER = np.array([[1.0, -0.5], [-0.5, 0.5]], dtype=np.float64)
 
 BOX_NONE = 0
-BOX_PERIODIC = 2
+BOX_SPHERE = 1          # steric sphere of radius box_len about the origin
+BOX_PERIODIC = 2        # periodic cube of edge box_len
 
 PREC_FP64 = 0
 PREC_FP32_SPLIT = 1
@@ -102,17 +103,21 @@ def straight_chains(chain_len, box_kind=BOX_NONE, box_len=0.0) -> np.ndarray:
     """Initial coordinates: every chain straight along +x with unit bonds.
 
     Chains are placed on a square grid in the (y, z) plane with spacing box_len / ceil(sqrt(M))
-    (or 4 bond lengths without a box), centred in the box.  Returns float64 [N, 3].
+    (or 4 bond lengths without a box), centred in the box; in a sphere the grid (spacing 2) and
+    every chain are centred on the origin.  Returns float64 [N, 3].
     """
     m = len(chain_len)
     side = int(np.ceil(np.sqrt(m)))
-    spacing = (box_len / side) if box_kind == BOX_PERIODIC else 4.0
+    spacing = {BOX_PERIODIC: box_len / side, BOX_SPHERE: 2.0}.get(box_kind, 4.0)
     out = []
     for c, n in enumerate(chain_len):
         gy, gz = c % side, c // side
-        x0 = (box_len - (n - 1)) / 2.0 if box_kind == BOX_PERIODIC else 0.0
+        x0 = {BOX_PERIODIC: (box_len - (n - 1)) / 2.0, BOX_SPHERE: -(n - 1) / 2.0}.get(box_kind, 0.0)
         y = (gy + 0.5) * spacing
         z = (gz + 0.5) * spacing
+        if box_kind == BOX_SPHERE:
+            y -= side * spacing / 2.0
+            z -= side * spacing / 2.0
         for i in range(n):
             out.append((x0 + i, y, z))
     return np.asarray(out, dtype=np.float64)
@@ -173,6 +178,24 @@ def cross_seeding(seed: int = 1702, walkers: int = 4096, precision: int = PREC_F
     sys_ = SystemSpec(chain_len=lens, types=types, e_lo=e_lo, n_bins=n_bins)
     return Workload(name="cross_seeding_4x9+4x10_L25", systems=[sys_], walkers_per_system=walkers,
                     k_bend=k_bend, k_tors=k_tors, box_kind=BOX_PERIODIC, box_len=25.0,
+                    precision=precision, resync_sweeps=100, rigid_per_sweep=1, seed=seed,
+                    n_iter=n_iter, n_sweeps=n_sweeps)
+
+
+def confined(seed: int = 1702, n_chains: int = 2, chain_len: int = 9, radius: float = 6.0,
+             walkers: int = 256, precision: int = PREC_FP32_SPLIT, n_iter: int = 10,
+             n_sweeps: int = 10000) -> Workload:
+    """`n_chains` copies of one `chain_len`-bead sequence in a steric sphere of the given radius
+    (the paper's container, Sec. 4), intra + inter LJ, rigid translations; a small radius makes
+    the wall matter."""
+    rng = np.random.default_rng([seed, 4])
+    seq = ab_sequence(rng, chain_len)
+    lens = [chain_len] * n_chains
+    e_lo, n_bins = default_window(sum(lens))
+    sys_ = SystemSpec(chain_len=lens, types=np.concatenate([seq] * n_chains), e_lo=e_lo,
+                      n_bins=n_bins)
+    return Workload(name=f"confined_{n_chains}x{chain_len}_R{radius:g}", systems=[sys_],
+                    walkers_per_system=walkers, box_kind=BOX_SPHERE, box_len=radius,
                     precision=precision, resync_sweeps=100, rigid_per_sweep=1, seed=seed,
                     n_iter=n_iter, n_sweeps=n_sweeps)
 
