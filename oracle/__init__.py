@@ -52,13 +52,17 @@ class _Weights(C.Structure):
 
 class _Moves(C.Structure):
     _fields_ = [("crank_max", C.c_double), ("cap_rho", C.c_double), ("trans_max", C.c_double),
-                ("rigid_per_sweep", C.c_int32)]
+                ("rigid_per_sweep", C.c_int32), ("pivot_per_sweep", C.c_int32),
+                ("pivot_max", C.c_double), ("rotate_per_sweep", C.c_int32),
+                ("rotate_max", C.c_double)]
 
 
 class _Counters(C.Structure):
     _fields_ = [("moves", C.c_int64), ("accepted", C.c_int64), ("rigid_moves", C.c_int64),
                 ("rigid_accepted", C.c_int64), ("window_rejects", C.c_int64),
-                ("max_drift", C.c_double)]
+                ("max_drift", C.c_double), ("pivot_moves", C.c_int64),
+                ("pivot_accepted", C.c_int64), ("rot_moves", C.c_int64),
+                ("rot_accepted", C.c_int64)]
 
 
 def _p(a, ct):
@@ -221,7 +225,9 @@ class Walker:
     def run(self, weights: Weights, moves: dict, n_sweeps: int, hist, accept_log=None,
             check_every: int = 0):
         mv = _Moves(moves["crank_max"], moves["cap_rho"], moves["trans_max"],
-                    moves["rigid_per_sweep"])
+                    moves["rigid_per_sweep"], moves.get("pivot_per_sweep", 0),
+                    moves.get("pivot_max", 0.0), moves.get("rotate_per_sweep", 0),
+                    moves.get("rotate_max", 0.0))
         sc = C.c_uint64(self.sweeps)
         e = C.c_double(self.energy)
         w = weights._c()
@@ -241,7 +247,9 @@ class Walker:
 
 def move_params(wl) -> dict:
     return dict(crank_max=wl.crank_max, cap_rho=wl.cap_rho, trans_max=wl.trans_max,
-                rigid_per_sweep=wl.rigid_per_sweep if wl.rigid_per_sweep else 0)
+                rigid_per_sweep=wl.rigid_per_sweep if wl.rigid_per_sweep else 0,
+                pivot_per_sweep=wl.pivot_per_sweep, pivot_max=wl.pivot_max,
+                rotate_per_sweep=wl.rotate_per_sweep, rotate_max=wl.rotate_max)
 
 
 def muca(wl, sys_index: int = 0, n_iter: Optional[int] = None, n_sweeps: Optional[int] = None,

@@ -96,6 +96,10 @@ typedef struct {
     double cap_rho;          /* end bead: new bond along d + rho g, g uniform on the unit sphere */
     double trans_max;        /* rigid chain translation: each axis uniform in [-t, t] */
     int32_t rigid_per_sweep; /* rigid translations after every sweep (multi-chain systems) */
+    int32_t pivot_per_sweep; /* pivots after every sweep */
+    double pivot_max;        /* pivot angle uniform in [-pivot_max, pivot_max] */
+    int32_t rotate_per_sweep;/* rigid chain rotations about the chain centre (multi-chain) */
+    double rotate_max;       /* rotation angle uniform in [-rotate_max, rotate_max] */
 } orc_moves;
 
 static int chain_of(const orc_system *s, int b)
@@ -288,7 +292,51 @@ typedef struct {
     int64_t rigid_moves, rigid_accepted; /* rigid chain translations */
     int64_t window_rejects;              /* proposals rejected for leaving the window */
     double max_drift;                    /* max |E_running - E_full| seen at checks */
+    int64_t pivot_moves, pivot_accepted; /* pivots */
+    int64_t rot_moves, rot_accepted;     /* rigid chain rotations */
 } orc_counters;
+
+/* Unit vector from two uniforms: z = 2 u1 - 1, azimuth 2 pi u2 (uniform on the sphere). */
+static void unit_from(double u1, double u2, double k[3])
+{
+    double z = 2.0 * u1 - 1.0;
+    double psi = 2.0 * M_PI * u2;
+    double sxy = sqrt(fmax(0.0, 1.0 - z * z));
+    k[0] = sxy * cos(psi); k[1] = sxy * sin(psi); k[2] = z;
+}
+
+/* x -> c + R (x - c): rotation by phi about the unit axis k through the point c (Rodrigues). */
+static void rotate_about(const double c[3], const double k[3], double phi, double *x)
+{
+    double v[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
+    double co = cos(phi), sn = sin(phi);
+    double kxv[3] = {k[1] * v[2] - k[2] * v[1], k[2] * v[0] - k[0] * v[2], k[0] * v[1] - k[1] * v[0]};
+    double kv = dot3(k, v);
+    for (int i = 0; i < 3; ++i) x[i] = c[i] + (v[i] * co + kxv[i] * sn + k[i] * kv * (1.0 - co));
+}
+
+/* Chain-level trial move on beads [lo, hi]: rotate them by phi about the axis k through c,
+ * accept with the Metropolis-MUCA test using Delta E = E(x') - E(x) (full energies), restore
+ * them if rejected.  Returns 1 if accepted; *k_new as for metropolis. */
+static int rotate_block(const orc_system *s, const orc_weights *w, double *pos, int lo, int hi,
+                        const double c[3], const double k[3], double phi, double u, double *e,
+                        int64_t *kb, int64_t *k_new)
+{
+    int nb = hi - lo + 1;
+    double *keep = (double *)malloc(sizeof(double) * 3 * (size_t)nb);
+    memcpy(keep, pos + 3 * lo, sizeof(double) * 3 * (size_t)nb);
+    double before = orc_energy(s, pos, NULL, NULL);
+    for (int i = lo; i <= hi; ++i) rotate_about(c, k, phi, pos + 3 * i);
+    double after = orc_energy(s, pos, NULL, NULL);
+    double e_new = *e + (after - before);
+    int acc = metropolis(w, *e, *kb, e_new, u, k_new);
+    for (int i = lo; i <= hi; ++i)
+        if (outside_sphere(s, pos + 3 * i)) acc = 0;
+    if (acc) { *e = e_new; *kb = *k_new; }
+    else memcpy(pos + 3 * lo, keep, sizeof(double) * 3 * (size_t)nb);
+    free(keep);
+    return acc;
+}
 
 /*
  * Run one walker for n_sweeps sweeps (Sec. 2.2 / 3.2, MONTE_CARLO).  A sweep is N single-bead
@@ -296,8 +344,16 @@ typedef struct {
  * (m, lo32(S), hi32(S), 0) under the walker's key: word 0 picks the bead (x0 * N) >> 32, words
  * 1-2 drive the proposal and word 3 the acceptance.  After the N moves of a multi-chain system
  * come rigid_per_sweep chain translations drawn from counters (r, lo, hi, 1) (chain and shift)
- * and (r, lo, hi, 2) (acceptance).  After every trial move, accepted or not, the bin of the
- * current energy is counted in hist (the paper updates the histogram at every simulation step).
+ * and (r, lo, hi, 2) (acceptance).  Then pivot_per_sweep pivots (the paper's pivotings): the
+ * block at (r, lo, hi, 3) picks the pivot bead p = (x0 * N) >> 32, the axis (words 1-2, uniform
+ * on the sphere) and the angle (word 3, uniform in +-pivot_max); the block at (r, lo, hi, 4)
+ * gives the acceptance (word 0) and the side (word 1 < 2^31: the beads after p in its chain,
+ * else those before it; for a chain end, the side that has beads), which is rotated about x_p.
+ * Then, for multi-chain systems, rotate_per_sweep rigid rotations of a chain (the paper's
+ * Galilean rotations) about its centre: blocks (r, lo, hi, 5) (chain (x0 * M) >> 32, axis,
+ * angle in +-rotate_max) and (r, lo, hi, 6) (acceptance).  After every trial move, accepted or
+ * not, the bin of the current energy is counted in hist (the paper updates the histogram at
+ * every simulation step).
  *
  * pos (N x 3) and *energy are updated in place; *sweep_counter advances by n_sweeps.
  * accept_log (optional, capacity log_cap bytes) gets one byte per single-bead trial move
@@ -385,6 +441,48 @@ int orc_run(const orc_system *s, const orc_weights *w, const orc_moves *mv, uint
                 }
                 free(keep);
                 cnt->rigid_moves++;
+                hist[k] += 1;
+            }
+        }
+        for (int rr = 0; rr < mv->pivot_per_sweep; ++rr) {
+            uint32_t ca[4] = {(uint32_t)rr, (uint32_t)S, (uint32_t)(S >> 32), 3u}, ra[4];
+            uint32_t cb[4] = {(uint32_t)rr, (uint32_t)S, (uint32_t)(S >> 32), 4u}, rb[4];
+            orc_philox(k0, k1, ca, ra);
+            orc_philox(k0, k1, cb, rb);
+            int p = (int)(((uint64_t)ra[0] * (uint64_t)n) >> 32);
+            int c = chain_of(s, p);
+            int first = s->chain_start[c], last = s->chain_start[c + 1] - 1;
+            int tail = (p == first) ? 1 : (p == last) ? 0 : (rb[1] < 0x80000000u);
+            int lo = tail ? p + 1 : first, hi = tail ? last : p - 1;
+            double axis[3], ctr[3] = {pos[3 * p], pos[3 * p + 1], pos[3 * p + 2]};
+            unit_from(u01(ra[1]), u01(ra[2]), axis);
+            double phi = mv->pivot_max * (2.0 * u01(ra[3]) - 1.0);
+            int64_t k_new;
+            int acc = rotate_block(s, w, pos, lo, hi, ctr, axis, phi, u01(rb[0]), &e, &k, &k_new);
+            if (acc) cnt->pivot_accepted++;
+            else if (k_new < 0) cnt->window_rejects++;
+            cnt->pivot_moves++;
+            hist[k] += 1;
+        }
+        if (s->n_chains > 1) {
+            for (int rr = 0; rr < mv->rotate_per_sweep; ++rr) {
+                uint32_t ca[4] = {(uint32_t)rr, (uint32_t)S, (uint32_t)(S >> 32), 5u}, ra[4];
+                uint32_t cb[4] = {(uint32_t)rr, (uint32_t)S, (uint32_t)(S >> 32), 6u}, rb[4];
+                orc_philox(k0, k1, ca, ra);
+                orc_philox(k0, k1, cb, rb);
+                int ch = (int)(((uint64_t)ra[0] * (uint64_t)s->n_chains) >> 32);
+                int lo = s->chain_start[ch], hi = s->chain_start[ch + 1] - 1;
+                double ctr[3] = {0, 0, 0}, axis[3];
+                for (int i = lo; i <= hi; ++i)
+                    for (int a = 0; a < 3; ++a) ctr[a] += pos[3 * i + a];
+                for (int a = 0; a < 3; ++a) ctr[a] /= (double)(hi - lo + 1);
+                unit_from(u01(ra[1]), u01(ra[2]), axis);
+                double phi = mv->rotate_max * (2.0 * u01(ra[3]) - 1.0);
+                int64_t k_new;
+                int acc = rotate_block(s, w, pos, lo, hi, ctr, axis, phi, u01(rb[0]), &e, &k, &k_new);
+                if (acc) cnt->rot_accepted++;
+                else if (k_new < 0) cnt->window_rejects++;
+                cnt->rot_moves++;
                 hist[k] += 1;
             }
         }

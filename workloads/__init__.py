@@ -74,6 +74,10 @@ class Workload:
     cap_rho: float = 0.8
     trans_max: float = 0.3
     rigid_per_sweep: int = 0
+    pivot_per_sweep: int = 0           # pivots after every sweep
+    pivot_max: float = np.pi / 6.0     # pivot angle uniform in [-pivot_max, pivot_max]
+    rotate_per_sweep: int = 0          # rigid chain rotations after every sweep (multi-chain)
+    rotate_max: float = np.pi / 6.0
     seed: int = 1702
     n_iter: int = 10
     n_sweeps: int = 100000
