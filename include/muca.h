@@ -59,7 +59,11 @@ enum { MUCA_PREC_FP64 = 0, MUCA_PREC_FP32_SPLIT = 1 };
  * Moves: one sweep = N single-bead trial moves (end bead: bond along d + cap_rho g with g
  * uniform on the sphere; interior bead: crankshaft by an angle uniform in +-crank_max), then
  * rigid_per_sweep translations of a random chain by up to +-trans_max per axis when the system
- * has more than one chain.  Random numbers: Philox4x32-10 keyed by (seed, walker).
+ * has more than one chain, pivot_per_sweep pivots (the beads on one side of a random bead p of
+ * its chain turn about x_p by an angle uniform in +-pivot_max about an axis uniform on the
+ * sphere) and, with more than one chain, rotate_per_sweep rotations of a random chain about its
+ * centre (angle uniform in +-rotate_max) — the pivotings and Galilean updates of the paper's
+ * update engine (Sec. 3.2).  Chain moves need several walkers per wave (below).  Random numbers: Philox4x32-10 keyed by (seed, walker).
  * precision: MUCA_PREC_FP64 evaluates everything in FP64; MUCA_PREC_FP32_SPLIT evaluates pair
  * terms in FP32 and keeps coordinates, the running energy, ln W and the recursion in FP64.
  * resync_sweeps > 0 recomputes every walker's energy in FP64 every resync_sweeps sweeps.
@@ -95,6 +99,10 @@ typedef struct {
     double drift_tol;
     double crank_max, cap_rho, trans_max;
     int32_t rigid_per_sweep;
+    int32_t pivot_per_sweep;
+    double pivot_max;
+    int32_t rotate_per_sweep;
+    double rotate_max;
     int32_t waves_per_block;
     int32_t walkers_per_wave;
     void *stream;
@@ -126,6 +134,8 @@ typedef struct {
     uint64_t window_rejects;              /* proposals that left the energy window */
     uint64_t sweeps;                      /* sweeps done (also the stream position) */
     double max_drift;                     /* largest |E_running - E_full| seen at a resync */
+    uint64_t pivot_moves, pivot_accepted; /* pivots */
+    uint64_t rot_moves, rot_accepted;     /* rigid chain rotations */
 } muca_walker_counters;
 
 /* Create a context: validates cfg, copies everything to the device, computes every walker's

@@ -38,7 +38,8 @@ class Muca:
                  walkers_per_system: int, k_lj_intra=4.0, k_lj_inter=4.0, k_bend=0.25,
                  k_tors=0.0, box_kind=0, box_len=0.0, bin_width=0.05, seed=1702,
                  precision=PREC_FP64, resync_sweeps=0, drift_tol=0.0, crank_max=np.pi / 3,
-                 cap_rho=0.8, trans_max=0.3, rigid_per_sweep=0, waves_per_block=0, walkers_per_wave=0,
+                 cap_rho=0.8, trans_max=0.3, rigid_per_sweep=0, pivot_per_sweep=0, pivot_max=0.5236,
+                 rotate_per_sweep=0, rotate_max=0.5236, waves_per_block=0, walkers_per_wave=0,
                  stream: Optional[int] = None):
         L = load()
         self._keep = dict(
@@ -64,7 +65,8 @@ class Muca:
             float(box_len), _ptr(k["elo"], C.c_double), _ptr(k["nb"], C.c_int32),
             float(bin_width), self.walkers, int(seed), int(precision), int(resync_sweeps),
             float(drift_tol), float(crank_max), float(cap_rho), float(trans_max),
-            int(rigid_per_sweep), int(waves_per_block), int(walkers_per_wave), stream)
+            int(rigid_per_sweep), int(pivot_per_sweep), float(pivot_max), int(rotate_per_sweep),
+            float(rotate_max), int(waves_per_block), int(walkers_per_wave), stream)
         h = C.c_void_p()
         check(L.muca_init(C.byref(cfg), C.byref(h)))
         self._h = h
@@ -85,7 +87,9 @@ class Muca:
                   bin_width=wl.bin_width, seed=wl.seed,
                   precision=wl.precision if precision is None else precision,
                   resync_sweeps=wl.resync_sweeps, crank_max=wl.crank_max, cap_rho=wl.cap_rho,
-                  trans_max=wl.trans_max, rigid_per_sweep=wl.rigid_per_sweep, stream=stream)
+                  trans_max=wl.trans_max, rigid_per_sweep=wl.rigid_per_sweep,
+                  pivot_per_sweep=wl.pivot_per_sweep, pivot_max=wl.pivot_max,
+                  rotate_per_sweep=wl.rotate_per_sweep, rotate_max=wl.rotate_max, stream=stream)
         kw.update(over)
         return cls([len(sp.chain_len) for sp in syss],
                    _np.concatenate([sp.chain_len for sp in syss]),

@@ -24,6 +24,8 @@ class MucaConfig(C.Structure):
                 ("seed", C.c_uint64), ("precision", C.c_int32), ("resync_sweeps", C.c_int32),
                 ("drift_tol", C.c_double), ("crank_max", C.c_double), ("cap_rho", C.c_double),
                 ("trans_max", C.c_double), ("rigid_per_sweep", C.c_int32),
+                ("pivot_per_sweep", C.c_int32), ("pivot_max", C.c_double),
+                ("rotate_per_sweep", C.c_int32), ("rotate_max", C.c_double),
                 ("waves_per_block", C.c_int32), ("walkers_per_wave", C.c_int32),
                 ("stream", C.c_void_p)]
 
@@ -36,7 +38,9 @@ class IterStats(C.Structure):
 class WalkerCounters(C.Structure):
     _fields_ = [("moves", C.c_uint64), ("accepted", C.c_uint64), ("rigid_moves", C.c_uint64),
                 ("rigid_accepted", C.c_uint64), ("window_rejects", C.c_uint64),
-                ("sweeps", C.c_uint64), ("max_drift", C.c_double)]
+                ("sweeps", C.c_uint64), ("max_drift", C.c_double),
+                ("pivot_moves", C.c_uint64), ("pivot_accepted", C.c_uint64),
+                ("rot_moves", C.c_uint64), ("rot_accepted", C.c_uint64)]
 
 
 class LaunchInfo(C.Structure):

@@ -43,7 +43,8 @@ struct WorkItem {
 };
 
 // Counter slots per walker in WalkerDev::cnt.
-enum { C_MOVES = 0, C_ACC, C_RIGID, C_RIGID_ACC, C_WREJ, C_SWEEPS, C_NCOUNT };
+enum { C_MOVES = 0, C_ACC, C_RIGID, C_RIGID_ACC, C_WREJ, C_SWEEPS, C_PIVOT, C_PIVOT_ACC, C_ROT,
+       C_ROT_ACC, C_NCOUNT };
 
 struct SweepArgs {
     const SysDev *sys;
@@ -68,6 +69,8 @@ struct SweepArgs {
     double bin_width, inv_bin;
     double crank_max, cap_rho, trans_max;
     int rigid_per_sweep;
+    int pivot_per_sweep, rotate_per_sweep;   // chain moves after every sweep (two-walker kernel)
+    double pivot_max, rotate_max;
     int resync_sweeps;
     double drift_tol;
     unsigned int seed_lo, seed_hi;

@@ -124,10 +124,15 @@ static size_t lds_need(const muca_ctx *ctx, long long bins, int n_sys, int wpb, 
                     : lds_for_bins(bins);
 }
 
+// Pivots and chain rotations exist in the several-walkers kernel only.
+static bool has_chain_moves(const muca_ctx *ctx) {
+    return ctx->args.pivot_per_sweep > 0 || ctx->args.rotate_per_sweep > 0;
+}
+
 // Walkers per wave the context can use: 4 needs a multiple of 4 walkers per system and at most
 // 64 beads (four slots of 16 lanes), 2 an even number of walkers; both need continuous weights.
 static bool pack_ok(const muca_ctx *ctx, int pack) {
-    if (pack == 1) return true;
+    if (pack == 1) return !has_chain_moves(ctx);
     if (!ctx->weights_continuous || ctx->W % pack != 0) return false;
     return pack == 2 || (pack == 4 && ctx->max_beads <= 64);
 }
@@ -236,6 +241,9 @@ static int refresh_continuity(muca_ctx *ctx) {
         }
     }
     ctx->weights_continuous = ok;
+    if (!ok && has_chain_moves(ctx))
+        return fail(ctx, MUCA_E_INVAL, "chain moves need continuous weights (ln W equal on both "
+                                       "sides of every bin edge)");
     if (!ok && ctx->pack > 1) {
         const int rc = build_schedule(ctx, std::min(16, ctx->W), true, 1);
         if (rc != MUCA_OK) return rc;
@@ -357,6 +365,9 @@ static int validate(const muca_config *c, std::string &why) {
     if (c->walkers_per_system < 1) { why = "walkers_per_system < 1"; return MUCA_E_INVAL; }
     if (c->precision != MUCA_PREC_FP64 && c->precision != MUCA_PREC_FP32_SPLIT) { why = "bad precision"; return MUCA_E_INVAL; }
     if (c->resync_sweeps < 0 || c->rigid_per_sweep < 0) { why = "negative resync/rigid count"; return MUCA_E_INVAL; }
+    if (c->pivot_per_sweep < 0 || c->rotate_per_sweep < 0) { why = "negative chain-move count"; return MUCA_E_INVAL; }
+    if ((c->pivot_per_sweep > 0 || c->rotate_per_sweep > 0) &&
+        (c->walkers_per_wave == 1 || c->walkers_per_system % 2 != 0)) { why = "chain moves need two or four walkers per wave (an even walkers_per_system)"; return MUCA_E_INVAL; }
     if (c->waves_per_block < 0 || c->waves_per_block > 16) { why = "waves_per_block must be 0..16"; return MUCA_E_INVAL; }
     if (c->walkers_per_wave != 0 && c->walkers_per_wave != 1 && c->walkers_per_wave != 2 &&
         c->walkers_per_wave != 4) { why = "walkers_per_wave must be 0, 1, 2 or 4"; return MUCA_E_INVAL; }
@@ -575,6 +586,10 @@ int muca_init(const muca_config *cfg, muca_ctx **out) {
     a.cap_rho = cfg->cap_rho;
     a.trans_max = cfg->trans_max;
     a.rigid_per_sweep = cfg->rigid_per_sweep;
+    a.pivot_per_sweep = cfg->pivot_per_sweep;
+    a.pivot_max = cfg->pivot_max;
+    a.rotate_per_sweep = cfg->rotate_per_sweep;
+    a.rotate_max = cfg->rotate_max;
     a.resync_sweeps = cfg->resync_sweeps;
     a.drift_tol = cfg->drift_tol > 0.0 ? cfg->drift_tol : 1e300;
     a.seed_lo = (unsigned int)cfg->seed;
@@ -597,11 +612,13 @@ int muca_init(const muca_config *cfg, muca_ctx **out) {
         ctx->err = "four walkers per wave need at most 64 beads per system";
         return bail(MUCA_E_INVAL);
     }
-    if (cfg->walkers_per_wave == 0 && cfg->waves_per_block > 8) pack = 1;
+    const bool chain = has_chain_moves(ctx);
+    if (cfg->walkers_per_wave == 0 && cfg->waves_per_block > 8 && !chain) pack = 1;
     int wpb = cfg->waves_per_block > 0 ? cfg->waves_per_block : (pack == 2 ? 8 : 16);
+    if (pack > 1) wpb = std::min(wpb, 8);
     wpb = std::max(1, std::min(wpb, ctx->W / pack));
     rc = build_schedule(ctx, wpb, true, pack);
-    if (rc != MUCA_OK && cfg->walkers_per_wave == 0 && pack > 1) {
+    if (rc != MUCA_OK && cfg->walkers_per_wave == 0 && pack > 1 && !chain) {
         pack = 1;      // the coordinate mirror does not fit beside the tables: one walker per wave
         wpb = std::min(cfg->waves_per_block > 0 ? cfg->waves_per_block : 16, ctx->W);
         rc = build_schedule(ctx, wpb, true, pack);
@@ -755,6 +772,10 @@ int muca_get_walkers(muca_ctx *ctx, int32_t sys, double *pos, double *energy,
             counters[w].window_rejects = cw[C_WREJ];
             counters[w].sweeps = cw[C_SWEEPS];
             counters[w].max_drift = dr[w];
+            counters[w].pivot_moves = cw[C_PIVOT];
+            counters[w].pivot_accepted = cw[C_PIVOT_ACC];
+            counters[w].rot_moves = cw[C_ROT];
+            counters[w].rot_accepted = cw[C_ROT_ACC];
         }
     }
     return MUCA_OK;

@@ -112,6 +112,27 @@ __device__ __forceinline__ double lnw_at(const double *le, int k, double t) {
     return l0 + (l1 - l0) * (t - (double)k);
 }
 
+// v -> R v for the rotation by the angle with cosine co and sine sn about the unit axis k
+// (Rodrigues' formula).
+__device__ __forceinline__ void rot3(double kx, double ky, double kz, double co, double sn,
+                                     double &vx, double &vy, double &vz) {
+    const double cx = ky * vz - kz * vy, cy = kz * vx - kx * vz, cz = kx * vy - ky * vx;
+    const double kv = (kx * vx + ky * vy + kz * vz) * (1.0 - co);
+    const double rx = vx * co + cx * sn + kx * kv;
+    const double ry = vy * co + cy * sn + ky * kv;
+    const double rz = vz * co + cz * sn + kz * kv;
+    vx = rx; vy = ry; vz = rz;
+}
+
+// Unit vector uniform on the sphere from two uniforms (z = 2 u1 - 1, azimuth 2 pi u2).
+__device__ __forceinline__ void unit_from(double u1, double u2, double &kx, double &ky, double &kz) {
+    const double z = 2.0 * u1 - 1.0;
+    double sp, cp;
+    sincos(2.0 * M_PI * u2, &sp, &cp);
+    const double sxy = sqrt(fmax(0.0, 1.0 - z * z));
+    kx = sxy * cp; ky = sxy * sp; kz = z;
+}
+
 // Per-move values drawn ahead by the lanes of a half (one move per lane) and read back by the
 // whole half: the rotation cosine / sine or the sphere vector, and ln u.
 struct Staged {
@@ -237,6 +258,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
     double lnw_cur = lnw_at(L.lw, k, (E - e_lo) * inv_eps);
 
     unsigned int n_mv = 0, n_acc = 0, n_rig = 0, n_rig_acc = 0, n_wrej = 0, run = 0;
+    unsigned int n_piv = 0, n_piv_acc = 0, n_rot = 0, n_rot_acc = 0;
     double max_drift = a.drift[w];
     const long long total = n_sweeps * (long long)N;
     long long done = 0;
@@ -465,6 +487,210 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                         ++run;
                     }
                 }
+                // ---- pivots: the beads on one side of a pivot bead p turn about x_p ----
+                for (int rr = 0; rr < a.pivot_per_sweep; ++rr) {
+                    const U4 ra = philox4x32_10((unsigned)rr, (unsigned)S, (unsigned)(S >> 32), 3u, k0, k1);
+                    const U4 rb = philox4x32_10((unsigned)rr, (unsigned)S, (unsigned)(S >> 32), 4u, k0, k1);
+                    const int p = (int)(((unsigned long long)ra.x * (unsigned long long)N) >> 32);
+                    const int infp = L.binfo[p];
+                    const int cp = bi_chain(infp);
+                    const int cs = sd.chain_start[cp], ce = sd.chain_start[cp + 1];
+                    const bool tail = bi_first(infp) || (!bi_last(infp) && rb.y < 0x80000000u);
+                    const int lo = tail ? p + 1 : cs, hi = tail ? ce - 1 : p - 1;
+                    double kx, ky, kz, sn, co;
+                    unit_from(u01(ra.y), u01(ra.z), kx, ky, kz);
+                    sincos(a.pivot_max * (2.0 * u01(ra.w) - 1.0), &sn, &co);
+                    const double ox = L.x[p], oy = L.y[p], oz = L.z[p];
+                    // new positions of this lane's moved beads
+                    double qx[SLOTS], qy[SLOTS], qz[SLOTS];
+                    A outside = 0;
+#pragma unroll
+                    for (int s = 0; s < SLOTS; ++s) {
+                        const int j = gl + G * s;
+                        double vx = px[s] - ox, vy = py[s] - oy, vz = pz[s] - oz;
+                        rot3(kx, ky, kz, co, sn, vx, vy, vz);
+                        const bool mv = j >= lo && j <= hi;
+                        qx[s] = mv ? ox + vx : px[s];
+                        qy[s] = mv ? oy + vy : py[s];
+                        qz[s] = mv ? oz + vz : pz[s];
+                        if (mv && a.sphere_r2 > 0.0 &&
+                            qx[s] * qx[s] + qy[s] * qy[s] + qz[s] * qz[s] > a.sphere_r2)
+                            outside += (A)1;
+                    }
+                    // pair terms between the moved beads (this lane's) and every bead that stays
+                    A pacc = 0;
+                    for (int jb = 0; jb < N; ++jb) {
+                        if (jb >= lo && jb <= hi) continue;          // uniform: both moved
+                        const double xj = L.x[jb], yj = L.y[jb], zj = L.z[jb];
+                        const int infj = L.binfo[jb];
+                        const int cj = bi_chain(infj), tj = bi_type(infj);
+#pragma unroll
+                        for (int s = 0; s < SLOTS; ++s) {
+                            const int j = gl + G * s;
+                            const bool same = chn[s] == cj;
+                            if (j >= lo && j <= hi && !(same && (j == jb + 1 || j + 1 == jb))) {
+                                double dxo = px[s] - xj, dyo = py[s] - yj, dzo = pz[s] - zj;
+                                double dxn = qx[s] - xj, dyn = qy[s] - yj, dzn = qz[s] - zj;
+                                if constexpr (PERIODIC) {
+                                    dxo = min_img(dxo, a.box_len, a.inv_box);
+                                    dyo = min_img(dyo, a.box_len, a.inv_box);
+                                    dzo = min_img(dzo, a.box_len, a.inv_box);
+                                    dxn = min_img(dxn, a.box_len, a.inv_box);
+                                    dyn = min_img(dyn, a.box_len, a.inv_box);
+                                    dzn = min_img(dzn, a.box_len, a.inv_box);
+                                }
+                                const double kk = same ? a.k_intra : a.k_inter;
+                                pacc += pair_d<FP64>(dxo, dyo, dzo, dxn, dyn, dzn, kk,
+                                                     kk * L.ctab[trow[s] + tj]);
+                            }
+                        }
+                    }
+                    // bending and torsion terms that pair a turned bond with a fixed one:
+                    // bonds b_k = x_{k+1} - x_k, the turned ones are b_p, b_{p+1} (tail side) or
+                    // b_{p-2}, b_{p-1} (head side)
+                    double djoint = 0.0;
+                    {
+                        const int i0 = max(p - 2, cs), i1 = max(p - 1, cs);
+                        const int i3 = min(p + 1, ce - 1), i4 = min(p + 2, ce - 1);
+                        double bx[4], by[4], bz[4];    // b_{p-2}, b_{p-1}, b_p, b_{p+1}
+                        const int ia[5] = {i0, i1, p, i3, i4};
+                        double xs[5], ys[5], zs[5];
+#pragma unroll
+                        for (int q5 = 0; q5 < 5; ++q5) { xs[q5] = L.x[ia[q5]]; ys[q5] = L.y[ia[q5]]; zs[q5] = L.z[ia[q5]]; }
+#pragma unroll
+                        for (int q4 = 0; q4 < 4; ++q4) {
+                            bx[q4] = xs[q4 + 1] - xs[q4]; by[q4] = ys[q4 + 1] - ys[q4]; bz[q4] = zs[q4 + 1] - zs[q4];
+                        }
+                        double rx[4], ry[4], rz[4];
+#pragma unroll
+                        for (int q4 = 0; q4 < 4; ++q4) {
+                            rx[q4] = bx[q4]; ry[q4] = by[q4]; rz[q4] = bz[q4];
+                            if ((q4 >= 2) == tail) rot3(kx, ky, kz, co, sn, rx[q4], ry[q4], rz[q4]);
+                        }
+                        auto dd = [&](int u, int v) {
+                            return (bx[u] * bx[v] + by[u] * by[v] + bz[u] * bz[v]) -
+                                   (rx[u] * rx[v] + ry[u] * ry[v] + rz[u] * rz[v]);
+                        };
+                        const bool m1 = p - 1 >= cs, m2 = p - 2 >= cs, p1 = p + 1 <= ce - 1, p2 = p + 2 <= ce - 1;
+                        if (m1 && p1) djoint += a.k_bend * dd(1, 2);
+                        if (m2 && p1) djoint += a.k_tors * dd(0, 2);
+                        if (m1 && p2) djoint += a.k_tors * dd(1, 3);
+                    }
+                    const double pdE = group_sum<G>(pacc) + djoint;
+                    const bool pin = group_sum<G>(outside) == 0.0;
+                    const double pEn = E + pdE;
+                    const double pt = (pEn - e_lo) * inv_eps;
+                    const bool pwin = (pt >= 0.0) && (pt < (double)K);
+                    const int pkn = pwin ? (int)pt : 0;
+                    const double plnw = lnw_at(L.lw, pkn, pt);
+                    const bool pok = pwin && pin && (log(u01(rb.x)) < plnw - lnw_cur);
+                    n_wrej += pwin ? 0u : 1u;
+                    ++n_piv;
+                    if (pok) {
+#pragma unroll
+                        for (int s = 0; s < SLOTS; ++s) {
+                            const int j = gl + G * s;
+                            px[s] = qx[s]; py[s] = qy[s]; pz[s] = qz[s];
+                            if (j >= lo && j <= hi) { L.x[j] = qx[s]; L.y[j] = qy[s]; L.z[j] = qz[s]; }
+                        }
+#pragma unroll
+                        for (int s = 0; s < SLOTS; ++s) {      // bonds from the new coordinates
+                            const int j = gl + G * s;
+                            if (j < N && !bi_last(inf[s])) {
+                                ux[s] = (A)(L.x[j + 1] - px[s]);
+                                uy[s] = (A)(L.y[j + 1] - py[s]);
+                                uz[s] = (A)(L.z[j + 1] - pz[s]);
+                            }
+                        }
+                        if (pkn != k) {
+                            if (gl == 0) atomicAdd(&L.hist[k], run);
+                            run = 0;
+                        }
+                        E = pEn; k = pkn; lnw_cur = plnw;
+                        ++n_piv_acc;
+                    }
+                    ++run;
+                }
+                // ---- rigid rotations of a whole chain about its centre ----
+                for (int rr = 0; M > 1 && rr < a.rotate_per_sweep; ++rr) {
+                    const U4 ra = philox4x32_10((unsigned)rr, (unsigned)S, (unsigned)(S >> 32), 5u, k0, k1);
+                    const U4 rb = philox4x32_10((unsigned)rr, (unsigned)S, (unsigned)(S >> 32), 6u, k0, k1);
+                    const int ch = (int)(((unsigned long long)ra.x * (unsigned long long)M) >> 32);
+                    const int cs = sd.chain_start[ch], ce = sd.chain_start[ch + 1];
+                    double kx, ky, kz, sn, co;
+                    unit_from(u01(ra.y), u01(ra.z), kx, ky, kz);
+                    sincos(a.rotate_max * (2.0 * u01(ra.w) - 1.0), &sn, &co);
+                    double ox = 0.0, oy = 0.0, oz = 0.0;
+                    for (int ib = cs; ib < ce; ++ib) { ox += L.x[ib]; oy += L.y[ib]; oz += L.z[ib]; }
+                    const double inv_n = 1.0 / (double)(ce - cs);
+                    ox *= inv_n; oy *= inv_n; oz *= inv_n;
+                    A racc = 0;
+                    bool rinside = true;
+                    for (int ib = cs; ib < ce; ++ib) {
+                        const double xi = L.x[ib], yi = L.y[ib], zi = L.z[ib];
+                        double vx = xi - ox, vy = yi - oy, vz = zi - oz;
+                        rot3(kx, ky, kz, co, sn, vx, vy, vz);
+                        const double xs = ox + vx, ys = oy + vy, zs = oz + vz;
+                        if (a.sphere_r2 > 0.0 && xs * xs + ys * ys + zs * zs > a.sphere_r2)
+                            rinside = false;
+                        const int ti = bi_type(L.binfo[ib]);
+#pragma unroll
+                        for (int s = 0; s < SLOTS; ++s) {
+                            const int j = gl + G * s;
+                            if (j < N && chn[s] != ch) {
+                                double dxo = xi - px[s], dyo = yi - py[s], dzo = zi - pz[s];
+                                double dxn = xs - px[s], dyn = ys - py[s], dzn = zs - pz[s];
+                                if constexpr (PERIODIC) {
+                                    dxo = min_img(dxo, a.box_len, a.inv_box);
+                                    dyo = min_img(dyo, a.box_len, a.inv_box);
+                                    dzo = min_img(dzo, a.box_len, a.inv_box);
+                                    dxn = min_img(dxn, a.box_len, a.inv_box);
+                                    dyn = min_img(dyn, a.box_len, a.inv_box);
+                                    dzn = min_img(dzn, a.box_len, a.inv_box);
+                                }
+                                racc += pair_d<FP64>(dxo, dyo, dzo, dxn, dyn, dzn, a.k_inter,
+                                                     a.k_inter * L.ctab[trow[s] + ti]);
+                            }
+                        }
+                    }
+                    const double rdE = group_sum<G>(racc);
+                    const double rEn = E + rdE;
+                    const double rt = (rEn - e_lo) * inv_eps;
+                    const bool rin = (rt >= 0.0) && (rt < (double)K);
+                    const int rkn = rin ? (int)rt : 0;
+                    const double rlnw = lnw_at(L.lw, rkn, rt);
+                    const bool rok = rin && rinside && (log(u01(rb.x)) < rlnw - lnw_cur);
+                    n_wrej += rin ? 0u : 1u;
+                    ++n_rot;
+                    if (rok) {
+#pragma unroll
+                        for (int s = 0; s < SLOTS; ++s) {
+                            const int j = gl + G * s;
+                            if (j < N && chn[s] == ch) {
+                                double vx = px[s] - ox, vy = py[s] - oy, vz = pz[s] - oz;
+                                rot3(kx, ky, kz, co, sn, vx, vy, vz);
+                                px[s] = ox + vx; py[s] = oy + vy; pz[s] = oz + vz;
+                                L.x[j] = px[s]; L.y[j] = py[s]; L.z[j] = pz[s];
+                            }
+                        }
+#pragma unroll
+                        for (int s = 0; s < SLOTS; ++s) {
+                            const int j = gl + G * s;
+                            if (j < N && chn[s] == ch && !bi_last(inf[s])) {
+                                ux[s] = (A)(L.x[j + 1] - px[s]);
+                                uy[s] = (A)(L.y[j + 1] - py[s]);
+                                uz[s] = (A)(L.z[j + 1] - pz[s]);
+                            }
+                        }
+                        if (rkn != k) {
+                            if (gl == 0) atomicAdd(&L.hist[k], run);
+                            run = 0;
+                        }
+                        E = rEn; k = rkn; lnw_cur = rlnw;
+                        ++n_rot_acc;
+                    }
+                    ++run;
+                }
                 ++S;
                 if (a.resync_sweeps > 0 && (S % (unsigned long long)a.resync_sweeps) == 0) {
                     const double Ef = full_energy_pair<G, SLOTS, PERIODIC>(a, N, L, px, py, pz, inf);
@@ -502,6 +728,10 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
         cnt[C_RIGID] += n_rig;
         cnt[C_RIGID_ACC] += n_rig_acc;
         cnt[C_WREJ] += n_wrej;
+        cnt[C_PIVOT] += n_piv;
+        cnt[C_PIVOT_ACC] += n_piv_acc;
+        cnt[C_ROT] += n_rot;
+        cnt[C_ROT_ACC] += n_rot_acc;
         cnt[C_SWEEPS] = S;
         a.drift[w] = max_drift;
     }

@@ -69,6 +69,10 @@ def _compare(lib, orc, wl, walkers, n_sweeps, weights_by_sys=None, log_moves=Non
             assert cnt["rigid_moves"][i] == ow.counters.rigid_moves
             assert cnt["rigid_accepted"][i] == ow.counters.rigid_accepted
             assert cnt["window_rejects"][i] == ow.counters.window_rejects
+            assert cnt["pivot_moves"][i] == ow.counters.pivot_moves
+            assert cnt["pivot_accepted"][i] == ow.counters.pivot_accepted
+            assert cnt["rot_moves"][i] == ow.counters.rot_moves
+            assert cnt["rot_accepted"][i] == ow.counters.rot_accepted
             assert cnt["sweeps"][i] == n_sweeps
     m.close()
 
@@ -131,6 +135,42 @@ def test_fp64_steric_sphere(lib, orc, pack):
     _compare(lib, orc, wl, walkers=_walkers(pack, 3), n_sweeps=500, pack=pack)
     wl = dataclasses.replace(workloads.single_chain(), box_kind=workloads.BOX_SPHERE, box_len=6.5)
     _compare(lib, orc, wl, walkers=_walkers(pack, 2), n_sweeps=1500, pack=pack)
+
+
+@pytest.mark.parametrize("pack", [2, 4])
+def test_fp64_pivots(lib, orc, pack):
+    """Pivots (the beads on one side of a random bead turn about it) after every sweep of a
+    13-bead chain: accept sequence, counters and coordinates match the oracle."""
+    import dataclasses
+    wl = dataclasses.replace(workloads.single_chain(), pivot_per_sweep=2)
+    _compare(lib, orc, wl, walkers=_walkers(pack, 4), n_sweeps=800, pack=pack)
+
+
+@pytest.mark.parametrize("make", [
+    lambda: workloads.aggregation(),                                    # periodic, 4 x 9
+    lambda: workloads.confined(radius=6.0),                            # steric sphere
+    lambda: workloads.cross_seeding()])                                 # 76 beads, torsion
+def test_fp64_pivots_and_chain_rotations(lib, orc, make):
+    import dataclasses
+    wl = dataclasses.replace(make(), pivot_per_sweep=1, rotate_per_sweep=1)
+    _compare(lib, orc, wl, walkers=2, n_sweeps=200, pack=2)
+
+
+def test_chain_moves_need_several_walkers_per_wave(lib):
+    import dataclasses
+    wl = dataclasses.replace(workloads.single_chain(), pivot_per_sweep=1)
+    for kw in (dict(walkers=3), dict(walkers=2, walkers_per_wave=1)):
+        with pytest.raises(lib.MucaError) as ei:
+            lib.Muca.from_workload(wl, workloads.initial_positions(wl), **kw)
+        assert "INVAL" in str(ei.value)
+    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=2)
+    sp = wl.systems[0]
+    rng = np.random.default_rng(3)
+    with pytest.raises(lib.MucaError) as ei:                          # discontinuous ln W
+        m.set_weights(0, rng.uniform(0, 1, sp.n_bins), rng.uniform(-1, 1, sp.n_bins),
+                      np.zeros(sp.n_bins))
+    assert "INVAL" in str(ei.value)
+    m.close()
 
 
 def test_initial_bead_outside_sphere_is_rejected(lib):
