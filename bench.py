@@ -145,6 +145,19 @@ def matched_error(stream):
     return out
 
 
+def chain_moves_leg(wl, stream, sweeps=2000, steps=2):
+    """The batched workload with one pivot after every sweep (the paper's pivotings): single-bead
+    moves and pivots per second, same kernels and schedule search."""
+    import dataclasses
+    w2 = dataclasses.replace(wl, pivot_per_sweep=1)
+    r = run_gpu(w2, w2.walkers_per_system, sweeps, steps, 1, stream)
+    sec = r["event_ms"] / 1e3
+    pivots = w2.walkers_per_system * len(w2.systems) * sweeps * steps
+    return {"pivot_per_sweep": 1, "sweeps_per_step": sweeps, "steps": steps,
+            "single_bead_moves_per_s": r["moves"] / sec, "pivots_per_s": pivots / sec,
+            "ms_per_step": r["event_ms"] / steps, "launch_plan": r["plan"]}
+
+
 def cpu_baseline(wl, target_s: float = 15.0):
     """FP64 oracle on one host core: one walker of every system, sweeps sized to ~target_s."""
     import oracle
@@ -216,6 +229,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-matched", action="store_true")
+    ap.add_argument("--no-chain", action="store_true", help="skip the pivot leg")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the launch plan given by --walkers-per-wave / --waves-per-block")
     ap.add_argument("--walkers-per-wave", type=int, default=0)
@@ -265,6 +279,8 @@ def main():
         out["batched_over_plain"] = value / plain
     if not args.no_matched:
         out["matched_error"] = matched_error(st)
+    if not args.no_chain:
+        out["with_pivots"] = chain_moves_leg(wl, st)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out))

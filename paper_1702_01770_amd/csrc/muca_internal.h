@@ -19,6 +19,11 @@ hipError_t launch_sweep_pair(const SweepArgs &a, bool fp64, int group, int slots
                              int pos_stride, hipStream_t st);
 size_t sweep_pair_lds_bytes(long long bins_total, int n_sys, int n_waves, int pos_stride,
                             int group);
+// The same with pivots / chain rotations compiled in (muca_sweep_pair_chain.hip).
+hipError_t launch_sweep_pair_chain(const SweepArgs &a, bool fp64, int group, int slots,
+                                   bool periodic, int n_items, int waves_per_block,
+                                   size_t lds_bytes, long long n_sweeps, int pos_stride,
+                                   hipStream_t st);
 hipError_t launch_walker_energy(const SweepArgs &a, int slots, bool periodic, int n_walkers,
                                 const int *walker_sys, hipStream_t st);
 

@@ -13,826 +13,11 @@
 // so).  That leaves room for a private 32-bit histogram per system in LDS, counted run-length
 // encoded (one LDS atomic whenever a walker changes bin) and added to the device histogram once
 // per launch.
-#include <type_traits>
-
-#include "muca_device.h"
-#include "muca_internal.h"
+//
+// This translation unit holds the variants without chain moves, the LDS size and the dispatch.
+#include "muca_sweep_pair_impl.h"
 
 namespace muca {
-
-namespace {
-
-
-template <bool FP64>
-using AccP = typename std::conditional<FP64, double, float>::type;
-
-__device__ __forceinline__ double min_img(double d, double L, double invL) {
-    return d - L * rint(d * invL);
-}
-
-template <bool FP64>
-__device__ __forceinline__ AccP<FP64> pair_d(double dxo, double dyo, double dzo, double dxn,
-                                             double dyn, double dzn, double k, double kc) {
-    if constexpr (FP64) {
-        const double r2o = dxo * dxo + dyo * dyo + dzo * dzo;
-        const double r2n = dxn * dxn + dyn * dyn + dzn * dzn;
-        const double so = 1.0 / r2o, sn = 1.0 / r2n;
-        const double s3o = so * so * so, s3n = sn * sn * sn;
-        return s3n * (k * s3n - kc) - s3o * (k * s3o - kc);
-    } else {
-        const float fxo = (float)dxo, fyo = (float)dyo, fzo = (float)dzo;
-        const float fxn = (float)dxn, fyn = (float)dyn, fzn = (float)dzn;
-        const float r2o = fxo * fxo + fyo * fyo + fzo * fzo;
-        const float r2n = fxn * fxn + fyn * fyn + fzn * fzn;
-        const float so = __builtin_amdgcn_rcpf(r2o), sn = __builtin_amdgcn_rcpf(r2n);
-        const float s3o = so * so * so, s3n = sn * sn * sn;
-        const float kf = (float)k, kcf = (float)kc;
-        return s3n * (kf * s3n - kcf) - s3o * (kf * s3o - kcf);
-    }
-}
-
-// Sum over the 32 lanes of each half, returned to every lane of that half: DPP butterfly to
-// the sum of each 16-lane row, then gfx950's row swap (rows 0<->1, 2<->3) adds the partner row.
-__device__ __forceinline__ double row_pair_sum(double v) {
-    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-    const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
-    const auto sl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-    const auto sh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-    const double a = __builtin_bit_cast(double, ((unsigned long long)sh[0] << 32) | sl[0]);
-    const double b = __builtin_bit_cast(double, ((unsigned long long)sh[1] << 32) | sl[1]);
-    return a + b;
-}
-__device__ __forceinline__ double half_sum_d(double v) {
-    v += dpp_d<0xB1>(v);
-    v += dpp_d<0x4E>(v);
-    v += dpp_d<0x141>(v);
-    v += dpp_d<0x140>(v);
-    return row_pair_sum(v);
-}
-// FP32 row sums, combined in FP64 (the 64-bit swap pattern above; the compiler folds the two
-// results of a 32-bit swap of one value into one).
-__device__ __forceinline__ double half_sum_f(float v) {
-    v += dpp_f<0xB1>(v);
-    v += dpp_f<0x4E>(v);
-    v += dpp_f<0x141>(v);
-    v += dpp_f<0x140>(v);
-    return row_pair_sum((double)v);
-}
-// Sum over the G lanes of each group, returned to every lane of the group: for G = 16 the DPP
-// row butterfly alone, for G = 32 followed by the row swap.
-template <int G>
-__device__ __forceinline__ double group_sum(double v) {
-    if constexpr (G == 32) {
-        return half_sum_d(v);
-    } else {
-        v += dpp_d<0xB1>(v);
-        v += dpp_d<0x4E>(v);
-        v += dpp_d<0x141>(v);
-        v += dpp_d<0x140>(v);
-        return v;
-    }
-}
-template <int G>
-__device__ __forceinline__ double group_sum(float v) {
-    if constexpr (G == 32) {
-        return half_sum_f(v);
-    } else {
-        v += dpp_f<0xB1>(v);
-        v += dpp_f<0x4E>(v);
-        v += dpp_f<0x141>(v);
-        v += dpp_f<0x140>(v);
-        return (double)v;
-    }
-}
-
-// ln W at t = (E - E_lo) / eps in bin k (t in [k, k+1) except at a tolerated window edge, where
-// the bin's line is extended), from the edge values le[k], le[k+1]
-__device__ __forceinline__ double lnw_at(const double *le, int k, double t) {
-    const double l0 = le[k], l1 = le[k + 1];
-    return l0 + (l1 - l0) * (t - (double)k);
-}
-
-// v -> R v for the rotation by the angle with cosine co and sine sn about the unit axis k
-// (Rodrigues' formula).
-__device__ __forceinline__ void rot3(double kx, double ky, double kz, double co, double sn,
-                                     double &vx, double &vy, double &vz) {
-    const double cx = ky * vz - kz * vy, cy = kz * vx - kx * vz, cz = kx * vy - ky * vx;
-    const double kv = (kx * vx + ky * vy + kz * vz) * (1.0 - co);
-    const double rx = vx * co + cx * sn + kx * kv;
-    const double ry = vy * co + cy * sn + ky * kv;
-    const double rz = vz * co + cz * sn + kz * kv;
-    vx = rx; vy = ry; vz = rz;
-}
-
-// Unit vector uniform on the sphere from two uniforms (z = 2 u1 - 1, azimuth 2 pi u2).
-__device__ __forceinline__ void unit_from(double u1, double u2, double &kx, double &ky, double &kz) {
-    const double z = 2.0 * u1 - 1.0;
-    double sp, cp;
-    sincos(2.0 * M_PI * u2, &sp, &cp);
-    const double sxy = sqrt(fmax(0.0, 1.0 - z * z));
-    kx = sxy * cp; ky = sxy * sp; kz = z;
-}
-
-// Per-move values drawn ahead by the lanes of a half (one move per lane) and read back by the
-// whole half: the rotation cosine / sine or the sphere vector, and ln u.
-struct Staged {
-    double q0, q1, q2, lnu;
-};
-
-struct PairLds {
-    const double *lw;          // ln W at the K + 1 bin edges of this walker's system
-    unsigned int *hist;        // LDS histogram of this walker's system
-    const int *binfo;          // bead descriptors of this walker's system
-    double *x, *y, *z;         // this walker's coordinates
-    const double *ctab;        // C_LJ[t][u], t, u < kMaxTypes
-    const void *kc;            // {kappa, kappa C_LJ}[intra / inter][t][u] in the accumulator type
-    int2 *sb;                  // staged bead index and descriptor of the next G moves (+1 spare)
-    Staged *sq;                // staged random values of the next G moves (+1 spare)
-};
-
-// Full FP64 energy of the walker of this group, from the LDS copy of its coordinates.
-template <int G, int SLOTS, bool PERIODIC>
-__device__ double full_energy_pair(const SweepArgs &a, int N, const PairLds &L,
-                                   const double (&px)[SLOTS], const double (&py)[SLOTS],
-                                   const double (&pz)[SLOTS], const int (&inf)[SLOTS]) {
-    const int gl = threadIdx.x & (G - 1);
-    double acc = 0.0;
-    for (int i = 0; i < N; ++i) {
-        const double xi = L.x[i], yi = L.y[i], zi = L.z[i];
-        const int infi = L.binfo[i];
-        const int ci = bi_chain(infi), ti = bi_type(infi);
-#pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
-            const int j = gl + G * s;
-            if (j < N && j > i) {
-                const bool same = bi_chain(inf[s]) == ci;
-                if (!(same && j == i + 1)) {
-                    double dx = xi - px[s], dy = yi - py[s], dz = zi - pz[s];
-                    if constexpr (PERIODIC) {
-                        dx = min_img(dx, a.box_len, a.inv_box);
-                        dy = min_img(dy, a.box_len, a.inv_box);
-                        dz = min_img(dz, a.box_len, a.inv_box);
-                    }
-                    const double k = same ? a.k_intra : a.k_inter;
-                    const double kc = k * L.ctab[bi_type(inf[s]) * kMaxTypes + ti];
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    const double sr = 1.0 / r2;
-                    const double s3 = sr * sr * sr;
-                    acc += s3 * (k * s3 - kc);
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-        const int j = gl + G * s;
-        if (j + 2 < N && !bi_last(inf[s]) && !bi_last(L.binfo[j + 1])) {
-            double b0[3] = {L.x[j + 1] - px[s], L.y[j + 1] - py[s], L.z[j + 1] - pz[s]};
-            double b1[3] = {L.x[j + 2] - L.x[j + 1], L.y[j + 2] - L.y[j + 1], L.z[j + 2] - L.z[j + 1]};
-            const double n0 = sqrt(b0[0] * b0[0] + b0[1] * b0[1] + b0[2] * b0[2]);
-            const double n1 = sqrt(b1[0] * b1[0] + b1[1] * b1[1] + b1[2] * b1[2]);
-            const double c = (b0[0] / n0) * (b1[0] / n1) + (b0[1] / n0) * (b1[1] / n1) +
-                             (b0[2] / n0) * (b1[2] / n1);
-            acc += a.k_bend * (1.0 - c);
-            if (j + 3 < N && !bi_last(L.binfo[j + 2])) {
-                double b2[3] = {L.x[j + 3] - L.x[j + 2], L.y[j + 3] - L.y[j + 2], L.z[j + 3] - L.z[j + 2]};
-                const double n2 = sqrt(b2[0] * b2[0] + b2[1] * b2[1] + b2[2] * b2[2]);
-                const double t = (b0[0] / n0) * (b2[0] / n2) + (b0[1] / n0) * (b2[1] / n2) +
-                                 (b0[2] / n0) * (b2[2] / n2);
-                acc += a.k_tors * (1.0 - t);
-            }
-        }
-    }
-    return group_sum<G>(acc);
-}
-
-template <bool FP64, int G, int SLOTS, bool PERIODIC>
-__device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const PairLds &L,
-                         long long n_sweeps) {
-    using A = AccP<FP64>;
-    using A2 = typename std::conditional<FP64, double2, float2>::type;
-    const int lane = threadIdx.x & 63, gl = lane & (G - 1);
-    // all groups of the wave sample the same system: these are wave-uniform
-    const int N = __builtin_amdgcn_readfirstlane(sd.n_beads);
-    const int M = __builtin_amdgcn_readfirstlane(sd.n_chains);
-    const int K = __builtin_amdgcn_readfirstlane(sd.n_bins);
-    const int npad = a.npad;
-    double *P = a.pos + (size_t)w * 3 * npad;
-    const double inv_eps = a.inv_bin;
-    const A2 *kct = reinterpret_cast<const A2 *>(L.kc);
-
-    // lane state: coordinates (FP64), bond to the next bead of the chain (accumulator type),
-    // descriptor, chain and row offset into the coupling table
-    double px[SLOTS], py[SLOTS], pz[SLOTS];
-    A ux[SLOTS], uy[SLOTS], uz[SLOTS];
-    int inf[SLOTS], chn[SLOTS], trow[SLOTS];
-#pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-        const int j = gl + G * s;
-        const bool alive = j < N;
-        px[s] = alive ? P[j] : 0.0;
-        py[s] = alive ? P[npad + j] : 0.0;
-        pz[s] = alive ? P[2 * npad + j] : 0.0;
-        inf[s] = alive ? L.binfo[j] : bead_info(0, 255, true, true);
-        chn[s] = bi_chain(inf[s]);
-        trow[s] = bi_type(inf[s]) * kMaxTypes;
-        if (alive && !bi_last(inf[s])) {
-            ux[s] = (A)(P[j + 1] - px[s]);
-            uy[s] = (A)(P[npad + j + 1] - py[s]);
-            uz[s] = (A)(P[2 * npad + j + 1] - pz[s]);
-        } else {
-            ux[s] = uy[s] = uz[s] = 0;
-        }
-    }
-
-    const double e_lo = sd.e_lo;
-    double E = a.energy[w];
-    unsigned long long *cnt = a.cnt + (size_t)w * C_NCOUNT;
-    unsigned long long S = cnt[C_SWEEPS];
-    const unsigned int k0 = a.seed_lo, k1 = a.seed_hi ^ (unsigned int)w;
-    int k = window_bin(E, e_lo, a.bin_width, inv_eps, K);
-    if (k < 0) {                                // this half's walker does no work
-        if (gl == 0) set_error(a.err, -4);
-        return;
-    }
-    double lnw_cur = lnw_at(L.lw, k, (E - e_lo) * inv_eps);
-
-    unsigned int n_mv = 0, n_acc = 0, n_rig = 0, n_rig_acc = 0, n_wrej = 0, run = 0;
-    unsigned int n_piv = 0, n_piv_acc = 0, n_rot = 0, n_rot_acc = 0;
-    double max_drift = a.drift[w];
-    const long long total = n_sweeps * (long long)N;
-    long long done = 0;
-    int m = 0;
-    unsigned int *alog = a.acc_log ? a.acc_log + (size_t)w * a.acc_log_words : nullptr;
-
-    while (done < total) {
-        // ---- each group draws the next (up to) G moves of its walker, one per lane ----
-        const int nblk = (int)min((long long)G, total - done);
-        {
-            const int idx = m + gl;
-            const unsigned long long Sl = S + (unsigned long long)(idx / N);
-            const int ml = idx % N;
-            const U4 r = philox4x32_10((unsigned int)ml, (unsigned int)Sl, (unsigned int)(Sl >> 32),
-                                       0u, k0, k1);
-            const int blane = (int)(((unsigned long long)r.x * (unsigned long long)N) >> 32);
-            const double u1 = u01(r.y), u2 = u01(r.z), u3 = u01(r.w);
-            // end bead: g uniform on the sphere; interior bead: rotation cosine / sine
-            const int binf_l = L.binfo[blane];
-            Staged q;
-            if (bi_first(binf_l) || bi_last(binf_l)) {
-                const double zc = 2.0 * u1 - 1.0;
-                double spsi, cpsi;
-                sincos(2.0 * M_PI * u2, &spsi, &cpsi);
-                const double sxy = sqrt(fmax(0.0, 1.0 - zc * zc));
-                q.q0 = sxy * cpsi; q.q1 = sxy * spsi; q.q2 = zc;
-            } else {
-                sincos(a.crank_max * (2.0 * u1 - 1.0), &q.q1, &q.q0);   // q0 = cos, q1 = sin
-                q.q2 = 0.0;
-            }
-            q.lnu = log(u3);
-            L.sb[gl] = make_int2(blane, binf_l);
-            L.sq[gl] = q;
-            if (gl == 0) L.sb[G] = make_int2(0, L.binfo[0]);    // spare entry for the last prefetch
-            __builtin_amdgcn_wave_barrier();
-        }
-        int2 bi_nx = L.sb[0];
-
-        for (int i = 0; i < nblk; ++i) {
-            // everything read here depends only on the staged draw of this move, so all of it is
-            // in flight at once; the draw of the next move is read now as well
-            const int b = bi_nx.x, infb = bi_nx.y;
-            const Staged q = L.sq[i];
-            bi_nx = L.sb[i + 1];
-            A2 kk[SLOTS];
-#pragma unroll
-            for (int s = 0; s < SLOTS; ++s)
-                kk[s] = kct[(chn[s] == bi_chain(infb) ? 0 : kMaxTypes * kMaxTypes) + trow[s] + bi_type(infb)];
-            const int tb = bi_type(infb), cb = bi_chain(infb);
-            const bool fst = bi_first(infb), lst = bi_last(infb);
-            const int bm = fst ? b : b - 1, bp = lst ? b : b + 1;
-            const double xbx = L.x[b], xby = L.y[b], xbz = L.z[b];
-            const double xmx = L.x[bm], xmy = L.y[bm], xmz = L.z[bm];
-            const double xpx = L.x[bp], xpy = L.y[bp], xpz = L.z[bp];
-            double nx, ny, nz;
-            if (fst || lst) {
-                // end bead: new bond along (x_b - x_a) + rho g, unit length, from anchor a
-                const double xax = fst ? xpx : xmx, xay = fst ? xpy : xmy, xaz = fst ? xpz : xmz;
-                const double vx = (xbx - xax) + a.cap_rho * q.q0;
-                const double vy = (xby - xay) + a.cap_rho * q.q1;
-                const double vz = (xbz - xaz) + a.cap_rho * q.q2;
-                const double rv = rsqrt(vx * vx + vy * vy + vz * vz);
-                nx = xax + vx * rv; ny = xay + vy * rv; nz = xaz + vz * rv;
-            } else {
-                // crankshaft: rotate x_b about the axis x_{b-1} -> x_{b+1} (Rodrigues)
-                const double c = q.q0, sn = q.q1;
-                const double ax = xpx - xmx, ay = xpy - xmy, az = xpz - xmz;
-                const double ra = rsqrt(ax * ax + ay * ay + az * az);
-                const double kx = ax * ra, ky = ay * ra, kz = az * ra;
-                const double vx = xbx - xmx, vy = xby - xmy, vz = xbz - xmz;
-                const double cx = ky * vz - kz * vy, cy = kz * vx - kx * vz, cz = kx * vy - ky * vx;
-                const double kv = kx * vx + ky * vy + kz * vz;
-                const double omc = 1.0 - c;
-                nx = xmx + (vx * c + cx * sn + kx * kv * omc);
-                ny = xmy + (vy * c + cy * sn + ky * kv * omc);
-                nz = xmz + (vz * c + cz * sn + kz * kv * omc);
-            }
-            // bond b-1 changes by -m, bond b by +m (m = x'_b - x_b): every other bending or
-            // torsion term that uses one of them changes by a multiple of u_j . m
-            const double mx = nx - xbx, my = ny - xby, mz = nz - xbz;
-            const A mxa = (A)mx, mya = (A)my, mza = (A)mz;
-            const A kbend = (A)a.k_bend, ktors = (A)a.k_tors;
-            const A c_m2 = lst ? -kbend : -kbend + ktors;   // j = b-2: bend(b-2), torsion(b-2)
-            const A c_p1 = fst ? kbend : kbend - ktors;     // j = b+1: bend(b), torsion(b-1)
-            A acc = 0;
-#pragma unroll
-            for (int s = 0; s < SLOTS; ++s) {
-                if (s > 0 && G * s >= N) break;          // wave-uniform: no bead in this slot
-                const int j = gl + G * s;
-                const int d = j - b;
-                const bool same = chn[s] == cb;
-                // skip the moved bead itself (d = 0, same chain), its bonded neighbours and empty
-                // lanes
-                const bool use = (j < N) && !(same && (unsigned)(d + 1) <= 2u);
-                double dxo = px[s] - xbx, dyo = py[s] - xby, dzo = pz[s] - xbz;
-                double dxn = px[s] - nx, dyn = py[s] - ny, dzn = pz[s] - nz;
-                if constexpr (PERIODIC) {
-                    dxo = min_img(dxo, a.box_len, a.inv_box);
-                    dyo = min_img(dyo, a.box_len, a.inv_box);
-                    dzo = min_img(dzo, a.box_len, a.inv_box);
-                    dxn = min_img(dxn, a.box_len, a.inv_box);
-                    dyn = min_img(dyn, a.box_len, a.inv_box);
-                    dzn = min_img(dzn, a.box_len, a.inv_box);
-                }
-                const A fxo = (A)dxo, fyo = (A)dyo, fzo = (A)dzo;
-                const A fxn = (A)dxn, fyn = (A)dyn, fzn = (A)dzn;
-                A r2o = fxo * fxo + fyo * fyo + fzo * fzo;
-                A r2n = fxn * fxn + fyn * fyn + fzn * fzn;
-                r2o = use ? r2o : (A)1;
-                r2n = use ? r2n : (A)1;
-                A so, sn2;
-                if constexpr (FP64) {
-                    so = 1.0 / r2o; sn2 = 1.0 / r2n;
-                } else {
-                    so = __builtin_amdgcn_rcpf(r2o); sn2 = __builtin_amdgcn_rcpf(r2n);
-                }
-                const A s3o = so * so * so, s3n = sn2 * sn2 * sn2;
-                const A t = s3n * (kk[s].x * s3n - kk[s].y) - s3o * (kk[s].x * s3o - kk[s].y);
-                acc += use ? t : (A)0;
-                A coef = (d == -2) ? c_m2 : (A)0;
-                coef = (d == 1) ? c_p1 : coef;
-                coef = (d == -3) ? -ktors : coef;
-                coef = (d == 2) ? ktors : coef;
-                coef = same ? coef : (A)0;
-                acc += coef * (ux[s] * mxa + uy[s] * mya + uz[s] * mza);
-            }
-            const double dE = group_sum<G>(acc);
-            const double En = E + dE;
-            const double t = (En - e_lo) * inv_eps;
-            const bool inwin = (t >= 0.0) && (t < (double)K);
-            const int kn = inwin ? (int)t : 0;
-            const double lnw_new = lnw_at(L.lw, kn, t);
-            // steric sphere: a bead may not leave it
-            const bool inside = a.sphere_r2 <= 0.0 || nx * nx + ny * ny + nz * nz <= a.sphere_r2;
-            const bool accept = inwin && inside && (q.lnu < lnw_new - lnw_cur);
-            n_wrej += inwin ? 0u : 1u;
-            if (alog && (long long)n_mv < a.acc_log_moves && accept && gl == 0)
-                atomicOr(&alog[n_mv >> 5], 1u << (n_mv & 31));
-            ++n_mv;
-            if (accept) {
-                // bonds b-1 and b recomputed from the coordinates (no accumulated rounding)
-                const A bmx = (A)(nx - xmx), bmy = (A)(ny - xmy), bmz = (A)(nz - xmz);
-                const A bpx = (A)(xpx - nx), bpy = (A)(xpy - ny), bpz = (A)(xpz - nz);
-#pragma unroll
-                for (int s = 0; s < SLOTS; ++s) {
-                    const int j = gl + G * s;
-                    const bool lo_b = (j == b - 1) && !fst, at_b = (j == b) && !lst;
-                    ux[s] = lo_b ? bmx : (at_b ? bpx : ux[s]);
-                    uy[s] = lo_b ? bmy : (at_b ? bpy : uy[s]);
-                    uz[s] = lo_b ? bmz : (at_b ? bpz : uz[s]);
-                    if (j == b) { px[s] = nx; py[s] = ny; pz[s] = nz; }
-                }
-                L.x[b] = nx; L.y[b] = ny; L.z[b] = nz;      // every lane of the half writes
-                if (kn != k) {
-                    if (gl == 0) atomicAdd(&L.hist[k], run);
-                    run = 0;
-                }
-                E = En; k = kn; lnw_cur = lnw_new;
-                ++n_acc;
-            }
-            ++run;
-
-            if (++m == N) {
-                m = 0;
-                if (M > 1) {
-                    for (int rr = 0; rr < a.rigid_per_sweep; ++rr) {
-                        const U4 r1 = philox4x32_10((unsigned)rr, (unsigned)S, (unsigned)(S >> 32), 1u, k0, k1);
-                        const U4 r2 = philox4x32_10((unsigned)rr, (unsigned)S, (unsigned)(S >> 32), 2u, k0, k1);
-                        const int ch = (int)(((unsigned long long)r1.x * (unsigned long long)M) >> 32);
-                        const double tx = a.trans_max * (2.0 * u01(r1.y) - 1.0);
-                        const double ty = a.trans_max * (2.0 * u01(r1.z) - 1.0);
-                        const double tz = a.trans_max * (2.0 * u01(r1.w) - 1.0);
-                        const double lnu_r = log(u01(r2.x));
-                        const int cs = sd.chain_start[ch], ce = sd.chain_start[ch + 1];
-                        A racc = 0;
-                        bool rinside = true;
-                        for (int ib = cs; ib < ce; ++ib) {
-                            const double xi = L.x[ib], yi = L.y[ib], zi = L.z[ib];
-                            const double xs = xi + tx, ys = yi + ty, zs = zi + tz;
-                            if (a.sphere_r2 > 0.0 && xs * xs + ys * ys + zs * zs > a.sphere_r2)
-                                rinside = false;
-                            const int ti = bi_type(L.binfo[ib]);
-#pragma unroll
-                            for (int s = 0; s < SLOTS; ++s) {
-                                const int j = gl + G * s;
-                                if (j < N && chn[s] != ch) {
-                                    double dxo = xi - px[s], dyo = yi - py[s], dzo = zi - pz[s];
-                                    double dxn = xs - px[s], dyn = ys - py[s], dzn = zs - pz[s];
-                                    if constexpr (PERIODIC) {
-                                        dxo = min_img(dxo, a.box_len, a.inv_box);
-                                        dyo = min_img(dyo, a.box_len, a.inv_box);
-                                        dzo = min_img(dzo, a.box_len, a.inv_box);
-                                        dxn = min_img(dxn, a.box_len, a.inv_box);
-                                        dyn = min_img(dyn, a.box_len, a.inv_box);
-                                        dzn = min_img(dzn, a.box_len, a.inv_box);
-                                    }
-                                    racc += pair_d<FP64>(dxo, dyo, dzo, dxn, dyn, dzn, a.k_inter,
-                                                         a.k_inter * L.ctab[trow[s] + ti]);
-                                }
-                            }
-                        }
-                        const double rdE = group_sum<G>(racc);
-                        const double rEn = E + rdE;
-                        const double rt = (rEn - e_lo) * inv_eps;
-                        const bool rin = (rt >= 0.0) && (rt < (double)K);
-                        const int rkn = rin ? (int)rt : 0;
-                        const double rlnw = lnw_at(L.lw, rkn, rt);
-                        const bool rok = rin && rinside && (lnu_r < rlnw - lnw_cur);
-                        n_wrej += rin ? 0u : 1u;
-                        ++n_rig;
-                        if (rok) {
-#pragma unroll
-                            for (int s = 0; s < SLOTS; ++s)
-                                if (chn[s] == ch) { px[s] += tx; py[s] += ty; pz[s] += tz; }
-                            for (int ib = cs; ib < ce; ++ib) {     // every lane of the half writes
-                                const double xo = L.x[ib], yo = L.y[ib], zo = L.z[ib];
-                                L.x[ib] = xo + tx; L.y[ib] = yo + ty; L.z[ib] = zo + tz;
-                            }
-                            if (rkn != k) {
-                                if (gl == 0) atomicAdd(&L.hist[k], run);
-                                run = 0;
-                            }
-                            E = rEn; k = rkn; lnw_cur = rlnw;
-                            ++n_rig_acc;
-                        }
-                        ++run;
-                    }
-                }
-                // ---- pivots: the beads on one side of a pivot bead p turn about x_p ----
-                for (int rr = 0; rr < a.pivot_per_sweep; ++rr) {
-                    const U4 ra = philox4x32_10((unsigned)rr, (unsigned)S, (unsigned)(S >> 32), 3u, k0, k1);
-                    const U4 rb = philox4x32_10((unsigned)rr, (unsigned)S, (unsigned)(S >> 32), 4u, k0, k1);
-                    const int p = (int)(((unsigned long long)ra.x * (unsigned long long)N) >> 32);
-                    const int infp = L.binfo[p];
-                    const int cp = bi_chain(infp);
-                    const int cs = sd.chain_start[cp], ce = sd.chain_start[cp + 1];
-                    const bool tail = bi_first(infp) || (!bi_last(infp) && rb.y < 0x80000000u);
-                    const int lo = tail ? p + 1 : cs, hi = tail ? ce - 1 : p - 1;
-                    double kx, ky, kz, sn, co;
-                    unit_from(u01(ra.y), u01(ra.z), kx, ky, kz);
-                    sincos(a.pivot_max * (2.0 * u01(ra.w) - 1.0), &sn, &co);
-                    const double ox = L.x[p], oy = L.y[p], oz = L.z[p];
-                    // new positions of this lane's moved beads
-                    double qx[SLOTS], qy[SLOTS], qz[SLOTS];
-                    A outside = 0;
-#pragma unroll
-                    for (int s = 0; s < SLOTS; ++s) {
-                        const int j = gl + G * s;
-                        double vx = px[s] - ox, vy = py[s] - oy, vz = pz[s] - oz;
-                        rot3(kx, ky, kz, co, sn, vx, vy, vz);
-                        const bool mv = j >= lo && j <= hi;
-                        qx[s] = mv ? ox + vx : px[s];
-                        qy[s] = mv ? oy + vy : py[s];
-                        qz[s] = mv ? oz + vz : pz[s];
-                        if (mv && a.sphere_r2 > 0.0 &&
-                            qx[s] * qx[s] + qy[s] * qy[s] + qz[s] * qz[s] > a.sphere_r2)
-                            outside += (A)1;
-                    }
-                    // pair terms between the moved beads (this lane's) and every bead that stays
-                    A pacc = 0;
-                    for (int jb = 0; jb < N; ++jb) {
-                        if (jb >= lo && jb <= hi) continue;          // uniform: both moved
-                        const double xj = L.x[jb], yj = L.y[jb], zj = L.z[jb];
-                        const int infj = L.binfo[jb];
-                        const int cj = bi_chain(infj), tj = bi_type(infj);
-#pragma unroll
-                        for (int s = 0; s < SLOTS; ++s) {
-                            const int j = gl + G * s;
-                            const bool same = chn[s] == cj;
-                            if (j >= lo && j <= hi && !(same && (j == jb + 1 || j + 1 == jb))) {
-                                double dxo = px[s] - xj, dyo = py[s] - yj, dzo = pz[s] - zj;
-                                double dxn = qx[s] - xj, dyn = qy[s] - yj, dzn = qz[s] - zj;
-                                if constexpr (PERIODIC) {
-                                    dxo = min_img(dxo, a.box_len, a.inv_box);
-                                    dyo = min_img(dyo, a.box_len, a.inv_box);
-                                    dzo = min_img(dzo, a.box_len, a.inv_box);
-                                    dxn = min_img(dxn, a.box_len, a.inv_box);
-                                    dyn = min_img(dyn, a.box_len, a.inv_box);
-                                    dzn = min_img(dzn, a.box_len, a.inv_box);
-                                }
-                                const double kk = same ? a.k_intra : a.k_inter;
-                                pacc += pair_d<FP64>(dxo, dyo, dzo, dxn, dyn, dzn, kk,
-                                                     kk * L.ctab[trow[s] + tj]);
-                            }
-                        }
-                    }
-                    // bending and torsion terms that pair a turned bond with a fixed one:
-                    // bonds b_k = x_{k+1} - x_k, the turned ones are b_p, b_{p+1} (tail side) or
-                    // b_{p-2}, b_{p-1} (head side)
-                    double djoint = 0.0;
-                    {
-                        const int i0 = max(p - 2, cs), i1 = max(p - 1, cs);
-                        const int i3 = min(p + 1, ce - 1), i4 = min(p + 2, ce - 1);
-                        double bx[4], by[4], bz[4];    // b_{p-2}, b_{p-1}, b_p, b_{p+1}
-                        const int ia[5] = {i0, i1, p, i3, i4};
-                        double xs[5], ys[5], zs[5];
-#pragma unroll
-                        for (int q5 = 0; q5 < 5; ++q5) { xs[q5] = L.x[ia[q5]]; ys[q5] = L.y[ia[q5]]; zs[q5] = L.z[ia[q5]]; }
-#pragma unroll
-                        for (int q4 = 0; q4 < 4; ++q4) {
-                            bx[q4] = xs[q4 + 1] - xs[q4]; by[q4] = ys[q4 + 1] - ys[q4]; bz[q4] = zs[q4 + 1] - zs[q4];
-                        }
-                        double rx[4], ry[4], rz[4];
-#pragma unroll
-                        for (int q4 = 0; q4 < 4; ++q4) {
-                            rx[q4] = bx[q4]; ry[q4] = by[q4]; rz[q4] = bz[q4];
-                            if ((q4 >= 2) == tail) rot3(kx, ky, kz, co, sn, rx[q4], ry[q4], rz[q4]);
-                        }
-                        auto dd = [&](int u, int v) {
-                            return (bx[u] * bx[v] + by[u] * by[v] + bz[u] * bz[v]) -
-                                   (rx[u] * rx[v] + ry[u] * ry[v] + rz[u] * rz[v]);
-                        };
-                        const bool m1 = p - 1 >= cs, m2 = p - 2 >= cs, p1 = p + 1 <= ce - 1, p2 = p + 2 <= ce - 1;
-                        if (m1 && p1) djoint += a.k_bend * dd(1, 2);
-                        if (m2 && p1) djoint += a.k_tors * dd(0, 2);
-                        if (m1 && p2) djoint += a.k_tors * dd(1, 3);
-                    }
-                    const double pdE = group_sum<G>(pacc) + djoint;
-                    const bool pin = group_sum<G>(outside) == 0.0;
-                    const double pEn = E + pdE;
-                    const double pt = (pEn - e_lo) * inv_eps;
-                    const bool pwin = (pt >= 0.0) && (pt < (double)K);
-                    const int pkn = pwin ? (int)pt : 0;
-                    const double plnw = lnw_at(L.lw, pkn, pt);
-                    const bool pok = pwin && pin && (log(u01(rb.x)) < plnw - lnw_cur);
-                    n_wrej += pwin ? 0u : 1u;
-                    ++n_piv;
-                    if (pok) {
-#pragma unroll
-                        for (int s = 0; s < SLOTS; ++s) {
-                            const int j = gl + G * s;
-                            px[s] = qx[s]; py[s] = qy[s]; pz[s] = qz[s];
-                            if (j >= lo && j <= hi) { L.x[j] = qx[s]; L.y[j] = qy[s]; L.z[j] = qz[s]; }
-                        }
-#pragma unroll
-                        for (int s = 0; s < SLOTS; ++s) {      // bonds from the new coordinates
-                            const int j = gl + G * s;
-                            if (j < N && !bi_last(inf[s])) {
-                                ux[s] = (A)(L.x[j + 1] - px[s]);
-                                uy[s] = (A)(L.y[j + 1] - py[s]);
-                                uz[s] = (A)(L.z[j + 1] - pz[s]);
-                            }
-                        }
-                        if (pkn != k) {
-                            if (gl == 0) atomicAdd(&L.hist[k], run);
-                            run = 0;
-                        }
-                        E = pEn; k = pkn; lnw_cur = plnw;
-                        ++n_piv_acc;
-                    }
-                    ++run;
-                }
-                // ---- rigid rotations of a whole chain about its centre ----
-                for (int rr = 0; M > 1 && rr < a.rotate_per_sweep; ++rr) {
-                    const U4 ra = philox4x32_10((unsigned)rr, (unsigned)S, (unsigned)(S >> 32), 5u, k0, k1);
-                    const U4 rb = philox4x32_10((unsigned)rr, (unsigned)S, (unsigned)(S >> 32), 6u, k0, k1);
-                    const int ch = (int)(((unsigned long long)ra.x * (unsigned long long)M) >> 32);
-                    const int cs = sd.chain_start[ch], ce = sd.chain_start[ch + 1];
-                    double kx, ky, kz, sn, co;
-                    unit_from(u01(ra.y), u01(ra.z), kx, ky, kz);
-                    sincos(a.rotate_max * (2.0 * u01(ra.w) - 1.0), &sn, &co);
-                    double ox = 0.0, oy = 0.0, oz = 0.0;
-                    for (int ib = cs; ib < ce; ++ib) { ox += L.x[ib]; oy += L.y[ib]; oz += L.z[ib]; }
-                    const double inv_n = 1.0 / (double)(ce - cs);
-                    ox *= inv_n; oy *= inv_n; oz *= inv_n;
-                    A racc = 0;
-                    bool rinside = true;
-                    for (int ib = cs; ib < ce; ++ib) {
-                        const double xi = L.x[ib], yi = L.y[ib], zi = L.z[ib];
-                        double vx = xi - ox, vy = yi - oy, vz = zi - oz;
-                        rot3(kx, ky, kz, co, sn, vx, vy, vz);
-                        const double xs = ox + vx, ys = oy + vy, zs = oz + vz;
-                        if (a.sphere_r2 > 0.0 && xs * xs + ys * ys + zs * zs > a.sphere_r2)
-                            rinside = false;
-                        const int ti = bi_type(L.binfo[ib]);
-#pragma unroll
-                        for (int s = 0; s < SLOTS; ++s) {
-                            const int j = gl + G * s;
-                            if (j < N && chn[s] != ch) {
-                                double dxo = xi - px[s], dyo = yi - py[s], dzo = zi - pz[s];
-                                double dxn = xs - px[s], dyn = ys - py[s], dzn = zs - pz[s];
-                                if constexpr (PERIODIC) {
-                                    dxo = min_img(dxo, a.box_len, a.inv_box);
-                                    dyo = min_img(dyo, a.box_len, a.inv_box);
-                                    dzo = min_img(dzo, a.box_len, a.inv_box);
-                                    dxn = min_img(dxn, a.box_len, a.inv_box);
-                                    dyn = min_img(dyn, a.box_len, a.inv_box);
-                                    dzn = min_img(dzn, a.box_len, a.inv_box);
-                                }
-                                racc += pair_d<FP64>(dxo, dyo, dzo, dxn, dyn, dzn, a.k_inter,
-                                                     a.k_inter * L.ctab[trow[s] + ti]);
-                            }
-                        }
-                    }
-                    const double rdE = group_sum<G>(racc);
-                    const double rEn = E + rdE;
-                    const double rt = (rEn - e_lo) * inv_eps;
-                    const bool rin = (rt >= 0.0) && (rt < (double)K);
-                    const int rkn = rin ? (int)rt : 0;
-                    const double rlnw = lnw_at(L.lw, rkn, rt);
-                    const bool rok = rin && rinside && (log(u01(rb.x)) < rlnw - lnw_cur);
-                    n_wrej += rin ? 0u : 1u;
-                    ++n_rot;
-                    if (rok) {
-#pragma unroll
-                        for (int s = 0; s < SLOTS; ++s) {
-                            const int j = gl + G * s;
-                            if (j < N && chn[s] == ch) {
-                                double vx = px[s] - ox, vy = py[s] - oy, vz = pz[s] - oz;
-                                rot3(kx, ky, kz, co, sn, vx, vy, vz);
-                                px[s] = ox + vx; py[s] = oy + vy; pz[s] = oz + vz;
-                                L.x[j] = px[s]; L.y[j] = py[s]; L.z[j] = pz[s];
-                            }
-                        }
-#pragma unroll
-                        for (int s = 0; s < SLOTS; ++s) {
-                            const int j = gl + G * s;
-                            if (j < N && chn[s] == ch && !bi_last(inf[s])) {
-                                ux[s] = (A)(L.x[j + 1] - px[s]);
-                                uy[s] = (A)(L.y[j + 1] - py[s]);
-                                uz[s] = (A)(L.z[j + 1] - pz[s]);
-                            }
-                        }
-                        if (rkn != k) {
-                            if (gl == 0) atomicAdd(&L.hist[k], run);
-                            run = 0;
-                        }
-                        E = rEn; k = rkn; lnw_cur = rlnw;
-                        ++n_rot_acc;
-                    }
-                    ++run;
-                }
-                ++S;
-                if (a.resync_sweeps > 0 && (S % (unsigned long long)a.resync_sweeps) == 0) {
-                    const double Ef = full_energy_pair<G, SLOTS, PERIODIC>(a, N, L, px, py, pz, inf);
-                    const double dr = fabs(Ef - E);
-                    max_drift = fmax(max_drift, dr);
-                    if (dr > a.drift_tol && gl == 0) set_error(a.err, -5);
-                    const int kf = window_bin(Ef, e_lo, a.bin_width, inv_eps, K);
-                    if (kf >= 0) {
-                        if (kf != k) {
-                            if (gl == 0) atomicAdd(&L.hist[k], run);
-                            run = 0;
-                        }
-                        E = Ef; k = kf;
-                        lnw_cur = lnw_at(L.lw, k, (E - e_lo) * inv_eps);
-                    } else if (gl == 0) {
-                        set_error(a.err, -4);
-                    }
-                }
-            }
-        }
-        done += nblk;
-        __builtin_amdgcn_wave_barrier();        // staged entries are rewritten by the next block
-    }
-    if (gl == 0 && run) atomicAdd(&L.hist[k], run);
-
-#pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-        const int j = gl + G * s;
-        if (j < N) { P[j] = px[s]; P[npad + j] = py[s]; P[2 * npad + j] = pz[s]; }
-    }
-    if (gl == 0) {
-        a.energy[w] = E;
-        cnt[C_MOVES] += n_mv;
-        cnt[C_ACC] += n_acc;
-        cnt[C_RIGID] += n_rig;
-        cnt[C_RIGID_ACC] += n_rig_acc;
-        cnt[C_WREJ] += n_wrej;
-        cnt[C_PIVOT] += n_piv;
-        cnt[C_PIVOT_ACC] += n_piv_acc;
-        cnt[C_ROT] += n_rot;
-        cnt[C_ROT_ACC] += n_rot_acc;
-        cnt[C_SWEEPS] = S;
-        a.drift[w] = max_drift;
-    }
-}
-
-}  // namespace
-
-
-// LDS layout (per workgroup), 16-byte items first: the {kappa, kappa C_LJ} table (intra, inter)
-// in the accumulator type; the staged draws of every walker; the C_LJ table; the x, y and z
-// coordinate mirrors of every walker (stride pos_stride); ln W at the bin edges of every system
-// of the workgroup (system i at lds_off[i] + i); the staged bead indices and descriptors of every
-// walker; the 32-bit histograms (system i at lds_off[i]); the bead descriptors of every system.
-template <bool FP64, int G, int SLOTS, bool PERIODIC>
-__global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_sweeps, int pos_stride) {
-    constexpr int kStage = G + 1;   // staged moves per walker (+1 spare for the prefetch)
-    constexpr int kPer = 64 / G;    // walkers per wave
-    using A = AccP<FP64>;
-    using A2 = typename std::conditional<FP64, double2, float2>::type;
-    extern __shared__ double2 lds_p[];
-    const WorkItem &wi = a.work[blockIdx.x];
-    const int ns = wi.n_sys;
-    const int n_waves = blockDim.x >> 6;
-    const int n_wl = kPer * n_waves;
-    const int bins_total = wi.lds_off[ns - 1] + a.sys[wi.sys[ns - 1]].n_bins;
-    A2 *kc = reinterpret_cast<A2 *>(lds_p);
-    Staged *sq = reinterpret_cast<Staged *>(lds_p + 2 * kMaxTypes * kMaxTypes);
-    double *ctab = reinterpret_cast<double *>(sq + (size_t)n_wl * kStage);
-    double *px = ctab + kMaxTypes * kMaxTypes;
-    double *py = px + (size_t)n_wl * pos_stride;
-    double *pz = py + (size_t)n_wl * pos_stride;
-    double *lw = pz + (size_t)n_wl * pos_stride;
-    int2 *sb = reinterpret_cast<int2 *>(lw + bins_total + ns);
-    unsigned int *hist = reinterpret_cast<unsigned int *>(sb + n_wl * kStage);
-    int *binfo = reinterpret_cast<int *>(hist + bins_total);
-    for (int i = 0; i < ns; ++i) {
-        const SysDev &sd = a.sys[wi.sys[i]];
-        const int off = wi.lds_off[i];
-        const int K = sd.n_bins;
-        for (int kk = threadIdx.x; kk <= K; kk += blockDim.x) {
-            // ln W at the lower edge of bin kk from bin kk's line; the top edge from the last bin
-            const int kb = kk < K ? kk : K - 1;
-            const double e = sd.e_lo + (double)kk * a.bin_width;
-            lw[off + i + kk] = -a.beta[sd.bin_off + kb] * e + a.alpha[sd.bin_off + kb];
-            if (kk < K) hist[off + kk] = 0u;
-        }
-        for (int j = threadIdx.x; j < kMaxBeads; j += blockDim.x)
-            binfo[i * kMaxBeads + j] = a.binfo[wi.sys[i] * kMaxBeads + j];
-    }
-    if (threadIdx.x < 2 * kMaxTypes * kMaxTypes) {
-        const int e = threadIdx.x % (kMaxTypes * kMaxTypes);
-        const int t = e / kMaxTypes, u = e % kMaxTypes;
-        const double c = (t < a.n_types && u < a.n_types) ? a.c_lj[t * a.n_types + u] : 0.0;
-        const double kap = threadIdx.x < kMaxTypes * kMaxTypes ? a.k_intra : a.k_inter;
-        if (threadIdx.x < kMaxTypes * kMaxTypes) ctab[e] = c;
-        A2 v;
-        v.x = (A)kap;
-        v.y = (A)(kap * c);
-        kc[threadIdx.x] = v;
-    }
-    const int wave = threadIdx.x >> 6;
-    const int grp = (threadIdx.x & 63) / G;
-    const int w0 = wi.walker[wave];
-    const int wl = kPer * wave + grp;
-    if (w0 >= 0) {                  // coordinate mirror of this half's walker
-        const int N = a.sys[wi.sys[wi.slot[wave]]].n_beads;
-        const double *P = a.pos + (size_t)(w0 + grp) * 3 * a.npad;
-        for (int j = threadIdx.x & (G - 1); j < N; j += G) {
-            px[(size_t)wl * pos_stride + j] = P[j];
-            py[(size_t)wl * pos_stride + j] = P[a.npad + j];
-            pz[(size_t)wl * pos_stride + j] = P[2 * a.npad + j];
-        }
-    }
-    __syncthreads();
-    if (w0 >= 0) {
-        const int i = wi.slot[wave];
-        const int sys = wi.sys[i];
-        const SysDev &sd = a.sys[sys];
-        PairLds L;
-        L.lw = lw + wi.lds_off[i] + i;
-        L.hist = hist + wi.lds_off[i];
-        L.binfo = binfo + i * kMaxBeads;
-        L.x = px + (size_t)wl * pos_stride;
-        L.y = py + (size_t)wl * pos_stride;
-        L.z = pz + (size_t)wl * pos_stride;
-        L.ctab = ctab;
-        L.kc = kc;
-        L.sb = sb + wl * kStage;
-        L.sq = sq + (size_t)wl * kStage;
-        run_pair<FP64, G, SLOTS, PERIODIC>(a, sd, w0 + grp, L, n_sweeps);
-    }
-    __syncthreads();
-    for (int i = 0; i < ns; ++i) {
-        const SysDev &sd = a.sys[wi.sys[i]];
-        const int off = wi.lds_off[i];
-        for (int kk = threadIdx.x; kk < sd.n_bins; kk += blockDim.x) {
-            const unsigned int h = hist[off + kk];
-            if (h) atomicAdd(&a.hist[sd.bin_off + kk], (unsigned long long)h);
-        }
-    }
-}
 
 size_t sweep_pair_lds_bytes(long long bins_total, int n_sys, int n_waves, int pos_stride,
                             int group) {
@@ -844,48 +29,14 @@ size_t sweep_pair_lds_bytes(long long bins_total, int n_sys, int n_waves, int po
            sizeof(int2) * n_wl * stage + sizeof(int) * (size_t)n_sys * kMaxBeads;
 }
 
-template <bool FP64, int G, int SLOTS, bool PERIODIC>
-static hipError_t launch_pair_t(const SweepArgs &a, int n_items, int waves, size_t lds,
-                                long long n_sweeps, int pos_stride, hipStream_t st) {
-    if (waves < 1 || waves > 8 || pos_stride < 1) return hipErrorInvalidValue;   // __launch_bounds__(512)
-    auto kern = k_sweep_pair<FP64, G, SLOTS, PERIODIC>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(n_items), dim3(64 * waves), lds, st, a, n_sweeps, pos_stride);
-    return hipGetLastError();
-}
-
-template <bool FP64, bool PERIODIC, int G>
-static hipError_t launch_pair_s(const SweepArgs &a, int slots, int n_items, int waves, size_t lds,
-                                long long n_sweeps, int pos_stride, hipStream_t st) {
-    switch (slots) {
-        case 1: return launch_pair_t<FP64, G, 1, PERIODIC>(a, n_items, waves, lds, n_sweeps, pos_stride, st);
-        case 2: return launch_pair_t<FP64, G, 2, PERIODIC>(a, n_items, waves, lds, n_sweeps, pos_stride, st);
-        case 3: return launch_pair_t<FP64, G, 3, PERIODIC>(a, n_items, waves, lds, n_sweeps, pos_stride, st);
-        case 4: return launch_pair_t<FP64, G, 4, PERIODIC>(a, n_items, waves, lds, n_sweeps, pos_stride, st);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <bool FP64, bool PERIODIC>
-static hipError_t launch_pair_g(const SweepArgs &a, int group, int slots, int n_items, int waves,
-                                size_t lds, long long n_sweeps, int pos_stride, hipStream_t st) {
-    if (group == 16)
-        return launch_pair_s<FP64, PERIODIC, 16>(a, slots, n_items, waves, lds, n_sweeps, pos_stride, st);
-    if (group == 32)
-        return launch_pair_s<FP64, PERIODIC, 32>(a, slots, n_items, waves, lds, n_sweeps, pos_stride, st);
-    return hipErrorInvalidValue;
-}
-
 hipError_t launch_sweep_pair(const SweepArgs &a, bool fp64, int group, int slots, bool periodic,
                              int n_items, int waves, size_t lds, long long n_sweeps, int pos_stride,
                              hipStream_t st) {
-    if (fp64)
-        return periodic ? launch_pair_g<true, true>(a, group, slots, n_items, waves, lds, n_sweeps, pos_stride, st)
-                        : launch_pair_g<true, false>(a, group, slots, n_items, waves, lds, n_sweeps, pos_stride, st);
-    return periodic ? launch_pair_g<false, true>(a, group, slots, n_items, waves, lds, n_sweeps, pos_stride, st)
-                    : launch_pair_g<false, false>(a, group, slots, n_items, waves, lds, n_sweeps, pos_stride, st);
+    if (a.pivot_per_sweep > 0 || a.rotate_per_sweep > 0)
+        return launch_sweep_pair_chain(a, fp64, group, slots, periodic, n_items, waves, lds,
+                                       n_sweeps, pos_stride, st);
+    return launch_pair_all<false>(a, fp64, group, slots, periodic, n_items, waves, lds, n_sweeps,
+                                  pos_stride, st);
 }
 
 }  // namespace muca
