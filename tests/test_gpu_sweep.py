@@ -375,3 +375,31 @@ def test_discontinuous_weights_fall_back_to_one_walker_per_wave(lib, orc):
     m.set_weights(0, Wc.beta, Wc.alpha, Wc.g)
     assert m.launch_info()["walkers_per_wave"] == 2
     m.close()
+
+
+@pytest.mark.parametrize("pack", [1, 2])
+def test_fp64_largest_system(lib, orc, pack):
+    """128 beads, the largest system a context holds (two bead slots of 64 lanes, or four of 32),
+    with a 2000-bin window around the starting energy."""
+    wl = workloads.single_chain(n=128)
+    sp = wl.systems[0]
+    sp.e_lo, sp.n_bins = -40.0, 2000
+    _compare(lib, orc, wl, walkers=2, n_sweeps=60, pack=pack)
+
+
+@pytest.mark.parametrize("pack", [1, 2, 4])
+def test_fp64_shortest_chain(lib, orc, pack):
+    """Three beads: one interior bead, two ends, a single non-bonded pair."""
+    wl = workloads.single_chain(n=3)
+    _compare(lib, orc, wl, walkers=_walkers(pack, 2), n_sweeps=1000, pack=pack)
+
+
+def test_zero_sweeps_is_a_no_op(lib):
+    wl = workloads.single_chain()
+    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=2)
+    p0, e0, c0 = m.walkers_state(0)
+    m.sweep(0)
+    p1, e1, c1 = m.walkers_state(0)
+    assert np.array_equal(p0, p1) and np.array_equal(e0, e1)
+    assert not m.histogram(0).any() and np.all(c1["moves"] == 0)
+    m.close()
