@@ -158,6 +158,118 @@ def chain_moves_leg(wl, stream, sweeps=2000, steps=2):
             "ms_per_step": r["event_ms"] / steps, "launch_plan": r["plan"]}
 
 
+def differentiation_flops_per_config(chain_len, periodic=True):
+    """Operations the energy forward + backward must perform for one stored configuration, each
+    unordered non-bonded pair once (Newton's third law) and each bending / torsion term once.
+    Forward: pair evaluation (13, +9 periodic) + accumulation 1; angle term 25 (two bond vectors
+    6, two norms 12, dot product and 1 - cos 7).  Backward: pair evaluation again, force scalar
+    kappa s (-12 s^6 + 6 C s^3) 5, force vector 3, added to both beads 6, coupling partial 1;
+    angle term 25 + derivatives with respect to both bonds 24 + scattered to its beads 9."""
+    n = int(np.sum(chain_len))
+    m = len(chain_len)
+    pairs = n * (n - 1) // 2 - (n - m)
+    angles = sum(max(0, L - 2) for L in chain_len) + sum(max(0, L - 3) for L in chain_len)
+    ev = 13 + (9 if periodic else 0)
+    fwd = pairs * (ev + 1) + angles * 25
+    bwd = pairs * (ev + 5 + 3 + 6 + 1) + angles * (25 + 24 + 9)
+    return fwd, bwd
+
+
+def differentiation_leg(stream, n_cfg=1_000_000, n_t=64, steps=3, warmup=1, sample_every=10):
+    """The differentiation path on stored configurations of the cross-seeding mixture (4 x 9 +
+    4 x 10 beads, periodic edge 25, bending + torsion): walkers of two short MUCA iterations are
+    stored every `sample_every` sweeps until n_cfg FP32 configurations sit in HBM with their
+    sampling weights ln W(E0).  One step = energy forward over all configurations, reweighted
+    <E>_T and C_V(T) at n_t temperatures in [0.1, 1.0], the reweighting backward for
+    L = sum_T (<E>_T + C_V(T)), and the energy backward (dE/dx and dE/dtheta).  Each kernel is
+    timed with HIP events on the library's stream."""
+    import torch
+
+    import paper_1702_01770_amd as P
+    import workloads
+    wl = workloads.cross_seeding()
+    sp = wl.systems[0]
+    W, N = wl.walkers_per_system, sp.n_beads
+    m = P.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=W,
+                             stream=stream.cuda_stream)
+    m.iterate(1000, 2)
+    b, a, _ = m.weights(0)
+    x = torch.empty((n_cfg, N, 3), dtype=torch.float32, device="cuda")
+    e0 = np.empty(n_cfg)
+    done = 0
+    while done < n_cfg:
+        m.sweep(sample_every)
+        pos, e, _ = m.walkers_state(0)
+        k = min(W, n_cfg - done)
+        x[done:done + k].copy_(torch.from_numpy(pos[:k].astype(np.float32)))
+        e0[done:done + k] = e[:k]
+        done += k
+    kb = np.clip(np.floor((e0 - sp.e_lo) / wl.bin_width).astype(np.int64), 0, sp.n_bins - 1)
+    lnw0 = torch.tensor(-b[kb] * e0 + a[kb], dtype=torch.float64, device="cuda")
+    theta = np.array([wl.c_lj[0, 1], wl.c_lj[1, 1], wl.k_bend, wl.k_tors])
+    temps = np.linspace(0.1, 1.0, n_t)
+    dev = "cuda"
+    E = torch.empty(n_cfg, dtype=torch.float64, device=dev)
+    mean = torch.empty(n_t, dtype=torch.float64, device=dev)
+    cv = torch.empty_like(mean)
+    mom = torch.empty(n_t, 3, dtype=torch.float64, device=dev)
+    ws = torch.empty(P.reweight_workspace_bytes(n_cfg, n_t), dtype=torch.uint8, device=dev)
+    g_mean = torch.ones(n_t, dtype=torch.float64, device=dev)
+    g_cv = torch.ones(n_t, dtype=torch.float64, device=dev)
+    gE = torch.empty_like(E)
+    gx = torch.empty_like(x)
+    gth = torch.empty(4, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    sid = stream.cuda_stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    tot = np.zeros(4)
+
+    def one(record):
+        if record:
+            ev[0].record(stream)
+        m.energy_fwd_ptr(0, x.data_ptr(), n_cfg, theta, E.data_ptr())
+        if record:
+            ev[1].record(stream)
+        P.reweight_fwd(E.data_ptr(), lnw0.data_ptr(), n_cfg, temps, mean.data_ptr(),
+                       cv.data_ptr(), mom.data_ptr(), ws.data_ptr(), ws.numel(), sid)
+        if record:
+            ev[2].record(stream)
+        P.reweight_bwd(E.data_ptr(), lnw0.data_ptr(), n_cfg, temps, mom.data_ptr(),
+                       g_mean.data_ptr(), g_cv.data_ptr(), gE.data_ptr(), sid)
+        if record:
+            ev[3].record(stream)
+        m.energy_bwd_ptr(0, x.data_ptr(), n_cfg, theta, gE.data_ptr(), gx.data_ptr(),
+                         gth.data_ptr())
+        if record:
+            ev[4].record(stream)
+            ev[4].synchronize()
+            for i in range(4):
+                tot[i] += ev[i].elapsed_time(ev[i + 1])
+
+    for _ in range(warmup):
+        one(False)
+    m.synchronize()
+    for _ in range(steps):
+        one(True)
+    m.close()
+    ms = tot / steps
+    fwd, bwd = differentiation_flops_per_config(sp.chain_len)
+    step_ms = float(ms.sum())
+    return {"workload": f"{n_cfg} stored configurations of the cross-seeding mixture "
+                        f"(4x9 + 4x10 beads, periodic L=25, bending + torsion), sampled every "
+                        f"{sample_every} sweeps from 4096 walkers; {n_t} temperatures in [0.1, 1]",
+            "steps": steps, "ms_per_step": step_ms,
+            "configs_per_s": n_cfg / (step_ms / 1e3),
+            "kernel_ms": {"energy_fwd": ms[0], "reweight_fwd": ms[1], "reweight_bwd": ms[2],
+                          "energy_bwd": ms[3]},
+            "algorithmic_flop_per_config": {"forward": fwd, "backward": bwd},
+            "energy_fwd_tflops": fwd * n_cfg / (ms[0] / 1e3) / 1e12,
+            "energy_bwd_tflops": bwd * n_cfg / (ms[3] / 1e3) / 1e12,
+            "peak_tflops": PEAK_FP32_TFLOPS,
+            "grad_theta": gth.cpu().tolist(),
+            "mean_E_at_T": [float(mean[0]), float(mean[-1])]}
+
+
 def cpu_baseline(wl, target_s: float = 15.0):
     """FP64 oracle on one host core: one walker of every system, sweeps sized to ~target_s."""
     import oracle
@@ -230,6 +342,10 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-matched", action="store_true")
     ap.add_argument("--no-chain", action="store_true", help="skip the pivot leg")
+    ap.add_argument("--no-diff", action="store_true", help="skip the differentiation leg")
+    ap.add_argument("--diff-only", action="store_true",
+                    help="run only the differentiation leg (profiling)")
+    ap.add_argument("--diff-configs", type=int, default=1_000_000)
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the launch plan given by --walkers-per-wave / --waves-per-block")
     ap.add_argument("--walkers-per-wave", type=int, default=0)
@@ -244,6 +360,11 @@ def main():
     st = make_stream()
     if args.calibrate_copy:
         copy_calibration()
+    if args.diff_only:
+        print(json.dumps({"differentiation": differentiation_leg(st, args.diff_configs,
+                                                                 steps=args.steps,
+                                                                 warmup=args.warmup)}))
+        return
     r = run_gpu(wl, wl.walkers_per_system, args.sweeps, args.steps, args.warmup, st,
                 autotune=not args.no_autotune, walkers_per_wave=args.walkers_per_wave,
                 waves_per_block=args.waves_per_block)
@@ -281,6 +402,8 @@ def main():
         out["matched_error"] = matched_error(st)
     if not args.no_chain:
         out["with_pivots"] = chain_moves_leg(wl, st)
+    if not args.no_diff:
+        out["differentiation"] = differentiation_leg(st, args.diff_configs)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out))
