@@ -68,6 +68,7 @@ struct EnergyArgs {
     const SysDev *sys;
     const int *binfo;
     int sys_index;
+    int n_beads;               // N of system sys_index
     const float *x;            // [n_cfg][N][3]
     long long n_cfg;
     double c_lj[kMaxTypes * kMaxTypes];

@@ -929,6 +929,7 @@ static int energy_args(muca_ctx *ctx, int32_t sys, const float *x, int64_t n_cfg
     e.sys = ctx->d_sys;
     e.binfo = ctx->d_binfo;
     e.sys_index = sys;
+    e.n_beads = ctx->sys[sys].n_beads;
     e.x = x;
     e.n_cfg = n_cfg;
     for (int i = 0; i < kMaxTypes * kMaxTypes; ++i) e.c_lj[i] = ctx->args.c_lj[i];

@@ -2,6 +2,8 @@
 energies of identical FP32 configurations within 1e-5 of the term scale, dE/dx and dE/dtheta
 against the oracle's analytic FP64 gradient, reweighted <E>_T and C_V(T) and their theta
 gradients against the oracle's fluctuation formulas, and finite differences in theta."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -74,6 +76,86 @@ def test_energy_and_gradients_vs_oracle(env, orc, make):
         assert np.max(np.abs(gx[i] - gref)) <= 2e-4 * gsc, (i, np.max(np.abs(gx[i] - gref)), gsc)
         gth_ref += ge[i].item() * dth
     assert np.allclose(gth, gth_ref, rtol=1e-4, atol=1e-6 * np.abs(gth_ref).max())
+    m.close()
+
+
+def _multi_chain(n_chains, chain_len, box_len):
+    """n_chains copies of one seeded sequence in a periodic cube (bending + torsion)."""
+    base = workloads.aggregation()
+    rng = np.random.default_rng([1702, 11])
+    seq = workloads.ab_sequence(rng, chain_len)
+    lens = [chain_len] * n_chains
+    e_lo, n_bins = workloads.default_window(sum(lens), 0.25)   # window table fits in LDS
+    sp = workloads.SystemSpec(chain_len=lens, types=np.concatenate([seq] * n_chains), e_lo=e_lo,
+                              n_bins=n_bins)
+    return dataclasses.replace(base, name="multi", systems=[sp], box_len=box_len, k_tors=0.1,
+                               bin_width=0.25, walkers_per_system=1)
+
+
+@pytest.mark.parametrize("make,n_cfg", [
+    (lambda: workloads.single_chain(n=3), 1),                 # smallest chain, one configuration
+    (lambda: workloads.single_chain(n=3), 7),
+    (lambda: workloads.single_chain(n=4), 5),                 # even N: the d = N/2 pair class
+    (lambda: workloads.single_chain(n=65), 61),               # odd N above one wave, ragged count
+    (lambda: _multi_chain(8, 16, 30.0), 9),                   # 128 beads (maximum), periodic
+    (lambda: _multi_chain(3, 3, 12.0), 6),                    # chains of 3 (no torsion term)
+])
+def test_energy_edge_shapes(env, orc, make, n_cfg):
+    """Energy, dE/dx and dE/dtheta on arbitrary overlap-free chains for the smallest and largest
+    systems, odd and even N and configuration counts that leave a workgroup partly empty."""
+    P, AG, torch = env
+    wl = make()
+    sp = wl.systems[0]
+    xs = workloads.random_bond_chains(29, n_cfg, sp.chain_len, box_len=wl.box_len)
+    x32 = xs.astype(np.float32)
+    x64 = x32.astype(np.float64)
+    theta = np.array([-0.4, 0.6, wl.k_bend + 0.01, wl.k_tors + 0.03])
+    cl = np.array([[1.0, theta[0]], [theta[0], theta[1]]])
+    s = orc.System(sp.chain_len, sp.types, cl, wl.k_lj_intra, wl.k_lj_inter, theta[2], theta[3],
+                   wl.box_kind, wl.box_len)
+    m = _ctx(P, wl)
+    xt = torch.tensor(x32, device="cuda", requires_grad=True)
+    th = torch.tensor(theta, dtype=torch.float64, device="cuda", requires_grad=True)
+    E = AG.EnergyFn.apply(xt, th, m, 0)
+    ge = torch.linspace(0.5, 1.5, n_cfg, dtype=torch.float64, device="cuda")
+    (E * ge).sum().backward()
+    Eg = E.detach().cpu().numpy()
+    gx = xt.grad.cpu().numpy().astype(np.float64)
+    gth_ref = np.zeros(4)
+    for i in range(n_cfg):
+        e64, grad, dth = s.energy_grad(x64[i])
+        _, _, scale = s.energy_parts(x64[i])
+        assert abs(Eg[i] - e64) <= 1e-5 * scale, (i, Eg[i], e64, scale)
+        gref = ge[i].item() * grad
+        gsc = np.abs(gref).max() + 1e-30
+        assert np.max(np.abs(gx[i] - gref)) <= 2e-4 * gsc
+        gth_ref += ge[i].item() * dth
+    assert np.allclose(th.grad.cpu().numpy(), gth_ref, rtol=1e-4,
+                       atol=1e-6 * np.abs(gth_ref).max() + 1e-12)
+    m.close()
+
+
+def test_energy_kernels_are_deterministic(env, orc):
+    """Every sum runs in a fixed order: two calls give bit-identical energies and gradients."""
+    P, AG, torch = env
+    wl = workloads.cross_seeding()
+    xs = workloads.random_bond_chains(31, 203, wl.systems[0].chain_len, box_len=wl.box_len)
+    m = _ctx(P, wl)
+    xt = torch.tensor(xs.astype(np.float32), device="cuda")
+    theta = np.array([-0.5, 0.5, wl.k_bend, wl.k_tors])
+    ge = torch.linspace(-1.0, 1.0, len(xs), dtype=torch.float64, device="cuda")
+    out = []
+    for _ in range(2):
+        E = torch.empty(len(xs), dtype=torch.float64, device="cuda")
+        gx = torch.empty_like(xt)
+        gth = torch.empty(4, dtype=torch.float64, device="cuda")
+        m.energy_fwd_ptr(0, xt.data_ptr(), len(xs), theta, E.data_ptr())
+        m.energy_bwd_ptr(0, xt.data_ptr(), len(xs), theta, ge.data_ptr(), gx.data_ptr(),
+                         gth.data_ptr())
+        m.synchronize()
+        out.append((E.cpu().numpy(), gx.cpu().numpy(), gth.cpu().numpy()))
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
     m.close()
 
 
