@@ -158,6 +158,26 @@ def chain_moves_leg(wl, stream, sweeps=2000, steps=2):
             "ms_per_step": r["event_ms"] / steps, "launch_plan": r["plan"]}
 
 
+def paper_systems_leg(stream, sweeps=2000, steps=2):
+    """The A/B strings the paper prints for its examples (Sec. 4.1, 4.2) in its steric spheres,
+    4096 walkers each, with one rigid translation, one pivot and one chain rotation after every
+    sweep: single-bead trial moves per second (the chain-level moves run on top)."""
+    import workloads
+    out = {}
+    for name in workloads.PAPER_SYSTEMS:
+        wl = workloads.paper_system(name)
+        r = run_gpu(wl, wl.walkers_per_system, sweeps, steps, 1, stream)
+        sec = r["event_ms"] / 1e3
+        per_sweep = wl.rigid_per_sweep + wl.pivot_per_sweep + wl.rotate_per_sweep
+        chain_moves = per_sweep * wl.walkers_per_system * sweeps * steps
+        out[name] = {"beads": wl.systems[0].n_beads, "sphere_radius": wl.box_len,
+                     "single_bead_moves_per_s": r["moves"] / sec,
+                     "chain_level_moves_per_s": chain_moves / sec,
+                     "ms_per_step": r["event_ms"] / steps, "launch_plan": r["plan"]}
+    out["sweeps_per_step"] = sweeps
+    return out
+
+
 def differentiation_flops_per_config(chain_len, periodic=True):
     """Operations the energy forward + backward must perform for one stored configuration, each
     unordered non-bonded pair once (Newton's third law) and each bending / torsion term once.
@@ -343,6 +363,7 @@ def main():
     ap.add_argument("--no-matched", action="store_true")
     ap.add_argument("--no-chain", action="store_true", help="skip the pivot leg")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation leg")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper-systems leg")
     ap.add_argument("--diff-only", action="store_true",
                     help="run only the differentiation leg (profiling)")
     ap.add_argument("--diff-configs", type=int, default=1_000_000)
@@ -402,6 +423,8 @@ def main():
         out["matched_error"] = matched_error(st)
     if not args.no_chain:
         out["with_pivots"] = chain_moves_leg(wl, st)
+    if not args.no_paper:
+        out["paper_systems"] = paper_systems_leg(st)
     if not args.no_diff:
         out["differentiation"] = differentiation_leg(st, args.diff_configs)
     if not args.no_cpu:

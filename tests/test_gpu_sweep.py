@@ -156,6 +156,15 @@ def test_fp64_pivots_and_chain_rotations(lib, orc, make):
     _compare(lib, orc, wl, walkers=2, n_sweeps=200, pack=2)
 
 
+@pytest.mark.parametrize("name,pack", [("abeta_dimer", 2), ("cross_human", 4), ("cross_rat", 2)])
+def test_fp64_paper_systems(lib, orc, name, pack):
+    """The A/B strings the paper prints for its examples, in its steric spheres, with single-bead
+    moves, rigid translations, pivots and chain rotations: accept sequences, histograms,
+    counters and coordinates match the oracle."""
+    wl = workloads.paper_system(name, walkers=4)
+    _compare(lib, orc, wl, walkers=_walkers(pack, 4), n_sweeps=300, pack=pack)
+
+
 def test_chain_moves_need_several_walkers_per_wave(lib):
     import dataclasses
     wl = dataclasses.replace(workloads.single_chain(), pivot_per_sweep=1)

@@ -11,7 +11,9 @@ Stand-ins for the paper's inputs (PHAST, arXiv:1702.01770, Sec. 4):
     the printed 9-10 bead sequences (Sec. 4.1, 4.2);
   * couplings follow the printed AB-limit parameter file (Sec. 4: r0 = 1, kappa_F = 0,
     kappa_C = 0.25, kappa_LJ_intra = kappa_LJ_inter = 4) and Eq. (1) for C_LJ;
-  * the paper's steric sphere is replaced by a periodic cube for the aggregation workloads.
+  * the paper's steric sphere is replaced by a periodic cube for the aggregation workloads;
+  * paper_system() runs the A/B strings the paper prints for its aggregation and cross-seeding
+    examples (Sec. 4.1, 4.2) in the paper's steric spheres, with its chain-level moves.
 
 Every generator takes an explicit integer seed and uses numpy's PCG64 stream, so every workload
 is reproducible bit for bit.
@@ -202,6 +204,39 @@ def confined(seed: int = 1702, n_chains: int = 2, chain_len: int = 9, radius: fl
                     walkers_per_system=walkers, box_kind=BOX_SPHERE, box_len=radius,
                     precision=precision, resync_sweeps=100, rigid_per_sweep=1, seed=seed,
                     n_iter=n_iter, n_sweeps=n_sweeps)
+
+
+# A/B strings and sphere radii of the paper's example systems (Sec. 4.1: the A-beta(25-33)
+# dimer in a sphere of radius 40; Sec. 4.2: A-beta(25-33) cross-seeded by human or rat
+# IAPP(20-29), two chains of each, in a sphere of radius 20).
+PAPER_SYSTEMS = {
+    "abeta_dimer": (["BBBBBAAAB", "BBBBBAAAB"], 40.0),
+    "cross_human": (["BBBABAAABB", "BBBABAAABB", "BBBBBAAAB", "BBBBBAAAB"], 20.0),
+    "cross_rat": (["BBBABAAAAA", "BBBABAAAAA", "BBBBBAAAB", "BBBBBAAAB"], 20.0),
+}
+
+
+def ab_from_string(seq: str) -> np.ndarray:
+    """'A'/'B' letters to type codes."""
+    return np.array([TYPE_A if c == "A" else TYPE_B for c in seq], dtype=np.uint8)
+
+
+def paper_system(name: str = "cross_human", walkers: int = 4096,
+                 precision: int = PREC_FP32_SPLIT, pivot_per_sweep: int = 1,
+                 rotate_per_sweep: int = 1, bin_width: float = 0.05, seed: int = 1702,
+                 n_iter: int = 10, n_sweeps: int = 10000) -> Workload:
+    """One of PAPER_SYSTEMS in its steric sphere with the paper's move set: single-bead moves,
+    rigid translations, pivots and rigid chain rotations (the last two per sweep as given)."""
+    seqs, radius = PAPER_SYSTEMS[name]
+    types = np.concatenate([ab_from_string(q) for q in seqs])
+    lens = [len(q) for q in seqs]
+    e_lo, n_bins = default_window(sum(lens), bin_width)
+    sys_ = SystemSpec(chain_len=lens, types=types, e_lo=e_lo, n_bins=n_bins)
+    return Workload(name=f"paper_{name}_R{radius:g}", systems=[sys_], walkers_per_system=walkers,
+                    box_kind=BOX_SPHERE, box_len=radius, bin_width=bin_width,
+                    precision=precision, resync_sweeps=100, rigid_per_sweep=1,
+                    pivot_per_sweep=pivot_per_sweep, rotate_per_sweep=rotate_per_sweep,
+                    seed=seed, n_iter=n_iter, n_sweeps=n_sweeps)
 
 
 def initial_positions(wl: Workload) -> List[np.ndarray]:
