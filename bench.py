@@ -178,6 +178,70 @@ def paper_systems_leg(stream, sweeps=2000, steps=2):
     return out
 
 
+# Latent heats and free-energy barriers the paper reports for its cross-seeding systems
+# (Sec. 4.2, intensive units): context for the physics leg, not a parity target (the paper's
+# force-field details and statistics differ).
+PAPER_MAXWELL = {"cross_human": {"latent": 0.513, "barrier": 0.034},
+                 "cross_rat": {"latent": 0.584, "barrier": 0.021}}
+
+
+def paper_physics_leg(stream, names, iters=1000, sweeps=2442, first=700, block=25):
+    """Full multicanonical runs of the paper's example systems as in Sec. 4: 4096 walkers share
+    about 10^7 sweeps per iteration (`sweeps` each), `iters` Berg iterations, then the
+    microcanonical analysis (Eqs. 4-8) of iterations [first, iters) in blocks of `block`:
+    Maxwell construction on beta(eps), latent heat and free-energy barrier per monomer, and
+    whether the caloric curve bends back (a region of negative microcanonical specific heat).
+    Flatness per iteration as the paper judges it: c_var < 5 % and peaks within 20 %."""
+    import paper_1702_01770_amd as P
+    import workloads
+    out = {}
+    for name in names:
+        wl = workloads.paper_system(name)
+        sp = wl.systems[0]
+        m = P.Muca.from_workload(wl, workloads.initial_positions(wl),
+                                 walkers=wl.walkers_per_system, stream=stream.cuda_stream)
+        m.autotune(probe_sweeps=20)
+        B = np.zeros((iters, sp.n_bins))
+        A = np.zeros((iters, sp.n_bins))
+        t0 = time.perf_counter()
+        for it in range(iters):
+            m.iterate(sweeps, 1)
+            B[it], A[it], _ = m.weights(0)
+            if (it + 1) % 50 == 0:
+                st = m.stats_history(it, 1)[0, 0]
+                print(f"[physics] {name} iteration {it + 1}/{iters} cvar {st[1]:.3f} "
+                      f"peak {st[2]:.3f} bins [{int(st[3])}, {int(st[4])}] "
+                      f"{time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+        st = m.stats_history(0, iters)[:, 0]
+        m.close()
+        flat = (st[:, 1] < 0.05) & (st[:, 2] < 0.20)
+        conv = next((i for i in range(iters) if flat[i:].all()), None)
+        lo = int(np.max(st[first:, 3])) + 5
+        hi = int(np.min(st[first:, 4])) - 5
+        if hi - lo < 20:
+            out[name] = {"error": f"visited range [{lo}, {hi}) too narrow to analyse",
+                         "flat_iterations": int(flat.sum())}
+            continue
+        res = P.microcanonical_analyze(B, A, sp.e_lo, wl.bin_width, lo, hi, first, iters, block,
+                                       5 * wl.bin_width, beta_c=0.0, tol_beta=1e-3, tol_l=0.02,
+                                       n_monomers=sp.n_beads)
+        dbeta = np.diff(res["beta"])
+        rec = {"beads": sp.n_beads, "sphere_radius": wl.box_len, "iterations": iters,
+               "sweeps_per_iteration": sweeps * wl.walkers_per_system,
+               "flat_iterations": int(flat.sum()), "flat_from": conv,
+               "eps_range": [float(res["E"][0]), float(res["E"][-1])],
+               "beta_c": res["beta_c"], "dbeta_c": res["dbeta_c"],
+               "latent_heat": res["latent"], "dlatent_heat": res["dlatent"],
+               "barrier": res["barrier"], "dbarrier": res["dbarrier"],
+               "backbending": bool(np.any(dbeta > 0)),
+               "negative_cv_points": int(np.sum(res["cv"] < 0)),
+               "wall_s": time.perf_counter() - t0}
+        if name in PAPER_MAXWELL:
+            rec["paper"] = PAPER_MAXWELL[name]
+        out[name] = rec
+    return out
+
+
 def differentiation_flops_per_config(chain_len, periodic=True):
     """Operations the energy forward + backward must perform for one stored configuration, each
     unordered non-bonded pair once (Newton's third law) and each bending / torsion term once.
@@ -364,6 +428,9 @@ def main():
     ap.add_argument("--no-chain", action="store_true", help="skip the pivot leg")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation leg")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper-systems leg")
+    ap.add_argument("--paper-physics", default="",
+                    help="comma-separated paper systems: only run their full MUCA + analysis")
+    ap.add_argument("--physics-iters", type=int, default=1000)
     ap.add_argument("--diff-only", action="store_true",
                     help="run only the differentiation leg (profiling)")
     ap.add_argument("--diff-configs", type=int, default=1_000_000)
@@ -381,6 +448,11 @@ def main():
     st = make_stream()
     if args.calibrate_copy:
         copy_calibration()
+    if args.paper_physics:
+        print(json.dumps({"paper_physics": paper_physics_leg(
+            st, args.paper_physics.split(","), iters=args.physics_iters,
+            first=int(0.7 * args.physics_iters), block=max(1, args.physics_iters // 40))}))
+        return
     if args.diff_only:
         print(json.dumps({"differentiation": differentiation_leg(st, args.diff_configs,
                                                                  steps=args.steps,

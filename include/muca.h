@@ -103,6 +103,8 @@ typedef struct {
     double pivot_max;
     int32_t rotate_per_sweep;
     double rotate_max;
+    double beta_min, beta_max;  /* when beta_max > beta_min, the weight recursion keeps every beta_k
+                                   in [beta_min, beta_max] (see muca_update_weights) */
     int32_t waves_per_block;
     int32_t walkers_per_wave;
     void *stream;
@@ -153,7 +155,10 @@ int muca_sweep(muca_ctx *ctx, int64_t n_sweeps);
 /* Weight recursion between iterations (Sec. 2.2): sums the walkers' histograms, applies
  * Berg's accumulated error-weighted recursion to beta, recomputes alpha for a continuous
  * ln W, records flatness statistics, saves the histogram as the "last" one and clears the
- * running one.  Synchronises the stream.  stats: host [n_systems] or NULL. */
+ * running one.  With cfg->beta_max > cfg->beta_min every updated beta_k is clamped to
+ * [beta_min, beta_max] (the weights then cover the canonical ensembles of that inverse-
+ * temperature range; bins below the lowest visited one copy its clamped slope).  Synchronises
+ * the stream.  stats: host [n_systems] or NULL. */
 int muca_update_weights(muca_ctx *ctx, muca_iter_stats *stats);
 
 /* Enqueue n_iter iterations of (n_sweeps sweeps + weight update) without host round trips; the

@@ -88,7 +88,7 @@ def lib():
                               C.POINTER(_Counters)]
         L.orc_berg_update.argtypes = [C.c_int32, C.c_double, C.c_double, C.POINTER(C.c_uint64),
                                       C.POINTER(C.c_double), C.POINTER(C.c_double),
-                                      C.POINTER(C.c_double)]
+                                      C.POINTER(C.c_double), C.c_double, C.c_double]
         L.orc_flatness.argtypes = [C.c_int32, C.POINTER(C.c_uint64), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                    C.POINTER(C.c_int32)]
@@ -179,7 +179,9 @@ class System:
 class Weights:
     """ln W(E) = -beta_k E + alpha_k on bins of width eps above e_lo (Eq. 8)."""
 
-    def __init__(self, e_lo, bin_width, n_bins, beta=None, alpha=None, g=None):
+    def __init__(self, e_lo, bin_width, n_bins, beta=None, alpha=None, g=None, beta_min=0.0,
+                 beta_max=0.0):
+        self.beta_min, self.beta_max = float(beta_min), float(beta_max)
         self.e_lo = float(e_lo)
         self.bin_width = float(bin_width)
         self.n_bins = int(n_bins)
@@ -195,10 +197,11 @@ class Weights:
         hist = np.ascontiguousarray(hist, dtype=np.uint64)
         lib().orc_berg_update(self.n_bins, self.e_lo, self.bin_width, _p(hist, C.c_uint64),
                               _p(self.beta, C.c_double), _p(self.alpha, C.c_double),
-                              _p(self.g, C.c_double))
+                              _p(self.g, C.c_double), self.beta_min, self.beta_max)
 
     def copy(self):
-        return Weights(self.e_lo, self.bin_width, self.n_bins, self.beta, self.alpha, self.g)
+        return Weights(self.e_lo, self.bin_width, self.n_bins, self.beta, self.alpha, self.g,
+                       self.beta_min, self.beta_max)
 
 
 def flatness(hist):
@@ -267,7 +270,7 @@ def muca(wl, sys_index: int = 0, n_iter: Optional[int] = None, n_sweeps: Optiona
     seed = wl.seed if seed is None else seed
     pos0 = workloads.initial_positions(wl)[sys_index]
     ws = [Walker(sysd, pos0, walker_offset + i, seed) for i in range(walkers)]
-    W = Weights(sp.e_lo, wl.bin_width, sp.n_bins)
+    W = Weights(sp.e_lo, wl.bin_width, sp.n_bins, beta_min=wl.beta_min, beta_max=wl.beta_max)
     mv = move_params(wl)
     out = dict(beta=[], alpha=[], g=[], hist=[], flat=[])
     for _ in range(n_iter):

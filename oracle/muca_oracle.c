@@ -499,7 +499,7 @@ int orc_run(const orc_system *s, const orc_weights *w, const orc_moves *mv, uint
 /* E_k = e_lo + k eps; beta_k is the slope of -ln W over bin k.                                 */
 /* ------------------------------------------------------------------------------------------ */
 void orc_berg_update(int32_t K, double e_lo, double eps, const uint64_t *H, double *beta,
-                     double *alpha, double *g)
+                     double *alpha, double *g, double beta_min, double beta_max)
 {
     for (int k = 0; k + 1 < K; ++k) {
         if (H[k] == 0 || H[k + 1] == 0) continue;
@@ -507,6 +507,10 @@ void orc_berg_update(int32_t K, double e_lo, double eps, const uint64_t *H, doub
         double g0 = h0 * h1 / (h0 + h1);          /* statistical weight of ln(H_{k+1}/H_k) */
         double ghat = g0 / (g[k] + g0);           /* share of this iteration in the average */
         beta[k] += ghat * (log(h1) - log(h0)) / eps;
+        if (beta_max > beta_min) {                /* inverse-temperature range of interest */
+            if (beta[k] < beta_min) beta[k] = beta_min;
+            if (beta[k] > beta_max) beta[k] = beta_max;
+        }
         g[k] += g0;
     }
     if (K >= 2) beta[K - 1] = beta[K - 2];

@@ -39,8 +39,8 @@ class Muca:
                  k_tors=0.0, box_kind=0, box_len=0.0, bin_width=0.05, seed=1702,
                  precision=PREC_FP64, resync_sweeps=0, drift_tol=0.0, crank_max=np.pi / 3,
                  cap_rho=0.8, trans_max=0.3, rigid_per_sweep=0, pivot_per_sweep=0, pivot_max=0.5236,
-                 rotate_per_sweep=0, rotate_max=0.5236, waves_per_block=0, walkers_per_wave=0,
-                 stream: Optional[int] = None):
+                 rotate_per_sweep=0, rotate_max=0.5236, beta_min=0.0, beta_max=0.0,
+                 waves_per_block=0, walkers_per_wave=0, stream: Optional[int] = None):
         L = load()
         self._keep = dict(
             cps=np.ascontiguousarray(chains_per_system, dtype=np.int32),
@@ -66,7 +66,8 @@ class Muca:
             float(bin_width), self.walkers, int(seed), int(precision), int(resync_sweeps),
             float(drift_tol), float(crank_max), float(cap_rho), float(trans_max),
             int(rigid_per_sweep), int(pivot_per_sweep), float(pivot_max), int(rotate_per_sweep),
-            float(rotate_max), int(waves_per_block), int(walkers_per_wave), stream)
+            float(rotate_max), float(beta_min), float(beta_max), int(waves_per_block),
+            int(walkers_per_wave), stream)
         h = C.c_void_p()
         check(L.muca_init(C.byref(cfg), C.byref(h)))
         self._h = h
@@ -89,7 +90,9 @@ class Muca:
                   resync_sweeps=wl.resync_sweeps, crank_max=wl.crank_max, cap_rho=wl.cap_rho,
                   trans_max=wl.trans_max, rigid_per_sweep=wl.rigid_per_sweep,
                   pivot_per_sweep=wl.pivot_per_sweep, pivot_max=wl.pivot_max,
-                  rotate_per_sweep=wl.rotate_per_sweep, rotate_max=wl.rotate_max, stream=stream)
+                  rotate_per_sweep=wl.rotate_per_sweep, rotate_max=wl.rotate_max,
+                  beta_min=getattr(wl, "beta_min", 0.0), beta_max=getattr(wl, "beta_max", 0.0),
+                  stream=stream)
         kw.update(over)
         return cls([len(sp.chain_len) for sp in syss],
                    _np.concatenate([sp.chain_len for sp in syss]),
@@ -126,13 +129,14 @@ class Muca:
         self._ck(self._L.muca_iterate(self._h, int(n_sweeps), int(n_iter)))
 
     def stats_history(self, first: int, count: int):
+        """[count, n_systems, 5]: moves, cvar, max_peak, k_min, k_max of iterations first.."""
         st = (_lib.IterStats * (self.n_systems * count))()
         self._ck(self._L.muca_get_stats_history(self._h, int(first), int(count), st))
-        out = np.zeros((count, self.n_systems, 4))
+        out = np.zeros((count, self.n_systems, 5))
         for i in range(count):
             for s in range(self.n_systems):
                 x = st[i * self.n_systems + s]
-                out[i, s] = (x.moves, x.cvar, x.max_peak, x.k_min)
+                out[i, s] = (x.moves, x.cvar, x.max_peak, x.k_min, x.k_max)
         return out
 
     def synchronize(self):

@@ -26,6 +26,7 @@ class MucaConfig(C.Structure):
                 ("trans_max", C.c_double), ("rigid_per_sweep", C.c_int32),
                 ("pivot_per_sweep", C.c_int32), ("pivot_max", C.c_double),
                 ("rotate_per_sweep", C.c_int32), ("rotate_max", C.c_double),
+                ("beta_min", C.c_double), ("beta_max", C.c_double),
                 ("waves_per_block", C.c_int32), ("walkers_per_wave", C.c_int32),
                 ("stream", C.c_void_p)]
 

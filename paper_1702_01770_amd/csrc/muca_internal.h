@@ -40,6 +40,7 @@ struct UpdateArgs {
     unsigned long long *hist_last;  // copy of the histogram the update used
     double *beta, *alpha, *g;
     double bin_width;
+    double beta_min, beta_max;      // recursion bounds, applied when beta_max > beta_min
     long long *iteration;           // device iteration counter
     IterStatsDev *stats;            // [stats_cap][n_sys]
     int stats_cap, n_sys;

@@ -60,6 +60,7 @@ struct muca_ctx {
     int pos_stride = 0;        // LDS coordinate stride of k_sweep_pair
     bool weights_continuous = true;   // ln W continuous at every bin edge (k_sweep_pair needs it)
     bool pack_fallback = false;       // one walker per wave because of discontinuous weights
+    double beta_min = 0.0, beta_max = 0.0;   // recursion bounds (off unless beta_max > beta_min)
     bool paired = true;
     size_t lds_limit = 0;
     size_t lds_bytes = 0;
@@ -294,6 +295,8 @@ static UpdateArgs update_args(muca_ctx *ctx) {
     u.alpha = ctx->d_alpha;
     u.g = ctx->d_g;
     u.bin_width = ctx->args.bin_width;
+    u.beta_min = ctx->beta_min;
+    u.beta_max = ctx->beta_max;
     u.iteration = ctx->d_iter;
     u.stats = ctx->d_stats;
     u.stats_cap = ctx->stats_cap;
@@ -373,6 +376,7 @@ static int validate(const muca_config *c, std::string &why) {
         c->walkers_per_wave != 4) { why = "walkers_per_wave must be 0, 1, 2 or 4"; return MUCA_E_INVAL; }
     if (c->walkers_per_wave > 1 && (c->walkers_per_system % c->walkers_per_wave) != 0) { why = "walkers_per_system must be a multiple of walkers_per_wave"; return MUCA_E_INVAL; }
     if (c->walkers_per_wave > 1 && c->waves_per_block > 8) { why = "more than one walker per wave allows at most 8 waves per block"; return MUCA_E_INVAL; }
+    if (!std::isfinite(c->beta_min) || !std::isfinite(c->beta_max)) { why = "beta bounds must be finite"; return MUCA_E_INVAL; }
     return MUCA_OK;
 }
 
@@ -590,6 +594,8 @@ int muca_init(const muca_config *cfg, muca_ctx **out) {
     a.pivot_max = cfg->pivot_max;
     a.rotate_per_sweep = cfg->rotate_per_sweep;
     a.rotate_max = cfg->rotate_max;
+    ctx->beta_min = cfg->beta_min;
+    ctx->beta_max = cfg->beta_max;
     a.resync_sweeps = cfg->resync_sweeps;
     a.drift_tol = cfg->drift_tol > 0.0 ? cfg->drift_tol : 1e300;
     a.seed_lo = (unsigned int)cfg->seed;

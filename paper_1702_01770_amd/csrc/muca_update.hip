@@ -64,7 +64,9 @@ __global__ void __launch_bounds__(1024) k_update(UpdateArgs u) {
             const double h0 = (double)h0u, h1 = (double)h1u;
             const double g0 = h0 * h1 / (h0 + h1);
             const double gh = g0 / (g[k] + g0);
-            beta[k] += gh * (log(h1) - log(h0)) / eps;
+            double b = beta[k] + gh * (log(h1) - log(h0)) / eps;
+            if (u.beta_max > u.beta_min) b = fmin(fmax(b, u.beta_min), u.beta_max);
+            beta[k] = b;
             g[k] += g0;
         }
     }

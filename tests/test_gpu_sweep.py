@@ -203,10 +203,16 @@ def test_four_walkers_per_wave_limits(lib):
     assert "INVAL" in str(ei.value)
 
 
-def test_weight_update_matches_oracle(lib, orc):
+@pytest.mark.parametrize("bounds", [(0.0, 0.0), (0.0, 2.0)])
+def test_weight_update_matches_oracle(lib, orc, bounds):
+    """Berg's recursion on the device against the oracle, unbounded and with the slopes kept in
+    an inverse-temperature range (bounds (0, 2) clip the steep first-iteration tails)."""
     wl = workloads.single_chain()
-    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=4, precision=0)
-    W = orc.Weights(wl.systems[0].e_lo, wl.bin_width, wl.systems[0].n_bins)
+    b_lo, b_hi = bounds
+    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=4, precision=0,
+                               beta_min=b_lo, beta_max=b_hi)
+    W = orc.Weights(wl.systems[0].e_lo, wl.bin_width, wl.systems[0].n_bins, beta_min=b_lo,
+                    beta_max=b_hi)
     for it in range(3):
         m.sweep(2000)
         H = m.histogram(0)
@@ -222,8 +228,10 @@ def test_weight_update_matches_oracle(lib, orc):
         assert st["iteration"] == it and st["moves"] == int(H.sum())
         assert (st["k_min"], st["k_max"]) == (lo, hi)
         assert st["cvar"] == pytest.approx(cv, rel=1e-12) and st["max_peak"] == pytest.approx(pk, rel=1e-12)
+        if b_hi > b_lo:
+            assert b.min() >= b_lo and b.max() <= b_hi
         # the oracle continues from the GPU's weights so the next histogram is comparable
-        W = orc.Weights(W.e_lo, W.bin_width, W.n_bins, b, a, g)
+        W = orc.Weights(W.e_lo, W.bin_width, W.n_bins, b, a, g, b_lo, b_hi)
     m.close()
 
 

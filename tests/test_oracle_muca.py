@@ -129,3 +129,28 @@ def test_muca_flattens_the_exact_three_bead_distribution(orc):
     assert np.std(q) < 0.04 and np.max(np.abs(q - 1)) < 0.12, (np.std(q), np.max(np.abs(q - 1)))
     cv, peak, _, _ = res["flat"][-1]
     assert cv < 0.15
+
+
+def test_bounded_recursion_clamps_to_the_inverse_temperature_range(orc):
+    """With bounds [beta_min, beta_max] every updated slope is the unbounded update clipped to the
+    range, the slopes below the lowest visited bin copy the clipped one, ln W stays continuous,
+    and bounds wide enough to hold every slope change nothing."""
+    H = np.array([0, 0, 1, 4, 40, 400, 500, 300, 300, 100], np.uint64)
+    free = orc.Weights(-5.0, 0.05, 10)
+    free.berg_update(H)
+    for lo, hi in ((0.0, 5.0), (-1.0, 40.0), (10.0, 30.0)):
+        W = orc.Weights(-5.0, 0.05, 10, beta_min=lo, beta_max=hi)
+        W.berg_update(H)
+        upd = np.nonzero((H[:-1] > 0) & (H[1:] > 0))[0]
+        assert np.allclose(W.beta[upd], np.clip(free.beta[upd], lo, hi), rtol=0, atol=1e-14)
+        assert np.all(W.beta[:2] == W.beta[2])
+        assert W.beta[-1] == W.beta[-2]
+        e = W.e_lo + np.arange(1, 10) * W.bin_width
+        assert np.allclose(-W.beta[:-1] * e + W.alpha[:-1], -W.beta[1:] * e + W.alpha[1:],
+                           rtol=0, atol=1e-12)
+        assert np.array_equal(W.g, free.g)
+    wide = orc.Weights(-5.0, 0.05, 10, beta_min=-1e3, beta_max=1e3)
+    wide.berg_update(H)
+    assert np.array_equal(wide.beta, free.beta) and np.array_equal(wide.alpha, free.alpha)
+    # a steep tail (1 -> 4 counts) would give beta = ln 4 / 0.05 = 27.7 below the visited range
+    assert free.beta[0] == pytest.approx(np.log(4.0) / 0.05)

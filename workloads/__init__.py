@@ -80,6 +80,8 @@ class Workload:
     pivot_max: float = np.pi / 6.0     # pivot angle uniform in [-pivot_max, pivot_max]
     rotate_per_sweep: int = 0          # rigid chain rotations after every sweep (multi-chain)
     rotate_max: float = np.pi / 6.0
+    beta_min: float = 0.0              # weight recursion keeps beta_k in [beta_min, beta_max]
+    beta_max: float = 0.0              # (off unless beta_max > beta_min)
     seed: int = 1702
     n_iter: int = 10
     n_sweeps: int = 100000
@@ -224,9 +226,12 @@ def ab_from_string(seq: str) -> np.ndarray:
 def paper_system(name: str = "cross_human", walkers: int = 4096,
                  precision: int = PREC_FP32_SPLIT, pivot_per_sweep: int = 1,
                  rotate_per_sweep: int = 1, bin_width: float = 0.05, seed: int = 1702,
-                 n_iter: int = 10, n_sweeps: int = 10000) -> Workload:
+                 beta_max: float = 6.0, n_iter: int = 10, n_sweeps: int = 10000) -> Workload:
     """One of PAPER_SYSTEMS in its steric sphere with the paper's move set: single-bead moves,
-    rigid translations, pivots and rigid chain rotations (the last two per sweep as given)."""
+    rigid translations, pivots and rigid chain rotations (the last two per sweep as given).
+    The weight recursion is bounded to inverse temperatures [0, beta_max]: the steep slopes that
+    sparse first-iteration tails produce would otherwise be copied to every lower bin and
+    freeze the walkers there."""
     seqs, radius = PAPER_SYSTEMS[name]
     types = np.concatenate([ab_from_string(q) for q in seqs])
     lens = [len(q) for q in seqs]
@@ -236,7 +241,8 @@ def paper_system(name: str = "cross_human", walkers: int = 4096,
                     box_kind=BOX_SPHERE, box_len=radius, bin_width=bin_width,
                     precision=precision, resync_sweeps=100, rigid_per_sweep=1,
                     pivot_per_sweep=pivot_per_sweep, rotate_per_sweep=rotate_per_sweep,
-                    seed=seed, n_iter=n_iter, n_sweeps=n_sweeps)
+                    beta_min=0.0, beta_max=beta_max, seed=seed, n_iter=n_iter,
+                    n_sweeps=n_sweeps)
 
 
 def initial_positions(wl: Workload) -> List[np.ndarray]:
