@@ -2,17 +2,14 @@
 // averages; not part of the paper).  One wave per configuration; its FP32 coordinates are staged
 // in LDS as float4 {x, y, z, bead info}.  Pair terms in FP32.
 //
-// Forward: the N (N - 1) / 2 unordered pairs are enumerated as (j, j + d mod N) with
-// d = 1 .. floor(N / 2) (the d = N / 2 class only for j < N / 2 when N is even), which lists every
-// pair exactly once; item t goes to j = t mod N, d = 1 + t div N and the items are dealt to the 64
-// lanes in turn, so every lane is busy and each pair is evaluated once.  Energies accumulate in
-// FP64 per lane, then a fixed-order wave reduction.
-//
-// Backward: one 16-lane DPP row per bead j; lane s of the row takes the partners i = s, s + 16,
-// ...  and sums the pair forces in FP32; the row sum (fixed butterfly order) is the pair part of
-// dE/dx_j.  Bending and torsion-like terms are evaluated once each, lane per term, their bond
-// derivatives written to LDS and gathered per bead in a fixed order, so the result does not
-// depend on scheduling.  dE/dtheta partials accumulate in FP64.
+// Pairs: lane (row, s), row = lane / 16, keeps the beads i = s + 16 m in registers and the
+// wave walks over the beads j = 4 p + row, so every unordered non-bonded pair (j, i > j) is
+// evaluated exactly once.  Forward: pair energies summed in FP32 per pass, in FP64 across passes,
+// then a fixed-order wave reduction.  Backward: the force on j is summed over its row (fixed DPP
+// butterfly), the opposite force on i stays in the lane's registers and is summed over the four
+// rows at the end; bending and torsion-like terms are evaluated once each, lane per term, their
+// bond derivatives written to LDS and gathered per bead in a fixed order.  Every sum has a fixed
+// order, so results do not depend on scheduling; dE/dtheta partials accumulate in FP64.
 //
 // theta = (C_AB, C_BB, kappa_bend, kappa_tors) for a two-letter lexicon.
 #include "muca_internal.h"
@@ -25,10 +22,6 @@ struct Theta {
     double c[kMaxTypes * kMaxTypes];
     double k_bend, k_tors;
 };
-
-__device__ __forceinline__ float mi_f(float d, float L, float invL, bool periodic) {
-    return periodic ? d - L * rintf(d * invL) : d;
-}
 
 __device__ __forceinline__ int info_of(float4 v) { return __builtin_bit_cast(int, v.w); }
 
@@ -74,12 +67,20 @@ __device__ __forceinline__ void stage(const EnergyArgs &a, long long cfg, int N,
                             __builtin_bit_cast(float, bi[b]));
 }
 
-// Pair table index: inter-chain entries follow the intra-chain ones.
-__device__ __forceinline__ int pair_slot(int infi, int infj) {
-    return (bi_chain(infi) != bi_chain(infj) ? kMaxTypes * kMaxTypes : 0) +
-           bi_type(infi) * kMaxTypes + bi_type(infj);
+// Pair tiling shared by both kernels.  Lane (row, s) of the wave, row = lane / 16, s = lane % 16,
+// keeps the beads i = s + 16 m (m < ceil(N / 16)) of the configuration in registers; the wave
+// walks over the beads j = 4 p + row (p = 0, 1, ...), the 16 lanes of a row holding one j, and
+// every lane evaluates its pairs (j, i) with i > j: each unordered non-bonded pair exactly once.
+// Slots m whose beads all precede the wave's four j are skipped (a wave-uniform branch).
+template <bool PERIODIC>
+__device__ __forceinline__ float sep(float d, float L, float invL) {
+    if constexpr (PERIODIC) return d - L * rintf(d * invL);
+    return d;
 }
 
+constexpr int kSlots = (kMaxBeads + 15) / 16;
+
+template <bool PERIODIC>
 __global__ void __launch_bounds__(64 * kEWaves) k_energy_fwd(EnergyArgs a, Theta th, int N) {
     extern __shared__ float4 e_lds[];
     __shared__ float2 coef[2 * kMaxTypes * kMaxTypes];   // {kappa, -kappa C}
@@ -95,30 +96,40 @@ __global__ void __launch_bounds__(64 * kEWaves) k_energy_fwd(EnergyArgs a, Theta
     }
     stage(a, cfg, N, lane, xs);
     __syncthreads();
-    const bool per = a.periodic != 0;
     const float L = (float)a.box_len, invL = (float)a.inv_box;
+    const int row = lane >> 4, seg = lane & 15, nm = (N + 15) >> 4;
+    float qx[kSlots], qy[kSlots], qz[kSlots];
+    int qi[kSlots];
+#pragma unroll
+    for (int m = 0; m < kSlots; ++m) {
+        const int i = seg + 16 * m;
+        const float4 q = xs[i < N ? i : N - 1];
+        qx[m] = q.x; qy[m] = q.y; qz[m] = q.z; qi[m] = info_of(q);
+    }
     double e_acc = 0.0;
-    const int n_items = N * (N - 1) / 2;
-    const int q64 = 64 / N, r64 = 64 % N;
-    int j = lane % N, d = 1 + lane / N;
-    for (int t = lane; t < n_items; t += 64) {
-        int i = j + d;
-        i = i >= N ? i - N : i;
-        const float4 pj = xs[j], pi = xs[i];
-        const int infj = info_of(pj), infi = info_of(pi);
-        const bool bonded = d == 1 && i != 0 && bi_chain(infi) == bi_chain(infj);
-        const float dx = mi_f(pj.x - pi.x, L, invL, per);
-        const float dy = mi_f(pj.y - pi.y, L, invL, per);
-        const float dz = mi_f(pj.z - pi.z, L, invL, per);
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        const float sr = __builtin_amdgcn_rcpf(r2);
-        const float s3 = sr * sr * sr;
-        const float2 k = coef[pair_slot(infi, infj)];
-        const float e = s3 * (k.x * s3 + k.y);
-        e_acc += bonded ? 0.0 : (double)e;
-        j += r64;
-        d += q64;
-        if (j >= N) { j -= N; d += 1; }
+    for (int jb = 0; jb < N; jb += 4) {
+        const int j = jb + row;
+        const bool jl = j < N;
+        const float4 pj = xs[jl ? j : N - 1];
+        const int infj = info_of(pj), cj = bi_chain(infj), tj = bi_type(infj);
+        const int m0 = jb >> 4;
+        float e = 0.0f;
+#pragma unroll
+        for (int m = 0; m < kSlots; ++m) {
+            if (m < m0 || m >= nm) continue;
+            const int i = seg + 16 * m;
+            const bool same = bi_chain(qi[m]) == cj;
+            const bool use = jl && i > j && i < N && !(same && i == j + 1);
+            const float dx = sep<PERIODIC>(pj.x - qx[m], L, invL);
+            const float dy = sep<PERIODIC>(pj.y - qy[m], L, invL);
+            const float dz = sep<PERIODIC>(pj.z - qz[m], L, invL);
+            const float r2 = use ? dx * dx + dy * dy + dz * dz : 1.0f;
+            const float sr = __builtin_amdgcn_rcpf(r2);
+            const float s3 = use ? sr * sr * sr : 0.0f;
+            const float2 k = coef[(same ? 0 : kMaxTypes * kMaxTypes) + bi_type(qi[m]) * kMaxTypes + tj];
+            e += s3 * (k.x * s3 + k.y);
+        }
+        e_acc += (double)e;
     }
     // bending (beads k, k+1, k+2) and torsion-like (k .. k+3) terms, one lane per k
     for (int k = lane; k < N; k += 64) {
@@ -136,6 +147,7 @@ __global__ void __launch_bounds__(64 * kEWaves) k_energy_fwd(EnergyArgs a, Theta
     if (live && lane == 0) a.energy[cfg] = E;
 }
 
+template <bool PERIODIC>
 __global__ void __launch_bounds__(64 * kEWaves) k_energy_bwd(EnergyArgs a, Theta th, int N) {
     extern __shared__ float4 e_lds[];
     __shared__ float4 coef[2 * kMaxTypes * kMaxTypes];   // {-12 kappa, 6 kappa C, w_AB, w_BB}
@@ -143,9 +155,10 @@ __global__ void __launch_bounds__(64 * kEWaves) k_energy_bwd(EnergyArgs a, Theta
     const long long cfg0 = (long long)blockIdx.x * kEWaves + wave;
     const bool live = cfg0 < a.n_cfg;
     const long long cfg = live ? cfg0 : a.n_cfg - 1;
-    float4 *xs = e_lds + wave * 6 * N;     // coordinates
-    float4 *gp = xs + N;                   // pair part of dE/dx per bead
-    float4 *bp = gp + N, *bq = bp + N;     // bending term k: dE/d(bond k), dE/d(bond k+1)
+    float4 *xs = e_lds + wave * 7 * N;     // coordinates
+    float4 *gp = xs + N;                   // pair forces on bead j from its pairs (j, i > j)
+    float4 *gi = gp + N;                   // pair forces on bead i from its pairs (j < i, i)
+    float4 *bp = gi + N, *bq = bp + N;     // bending term k: dE/d(bond k), dE/d(bond k+1)
     float4 *tp = bq + N, *tq = tp + N;     // torsion term k: dE/d(bond k), dE/d(bond k+2)
     if (threadIdx.x < 2 * kMaxTypes * kMaxTypes) {
         const int t = threadIdx.x % (kMaxTypes * kMaxTypes);
@@ -158,42 +171,62 @@ __global__ void __launch_bounds__(64 * kEWaves) k_energy_bwd(EnergyArgs a, Theta
     }
     stage(a, cfg, N, lane, xs);
     __syncthreads();
-    const bool per = a.periodic != 0;
     const float L = (float)a.box_len, invL = (float)a.inv_box;
-    const int row = lane >> 4, seg = lane & 15;
+    const int row = lane >> 4, seg = lane & 15, nm = (N + 15) >> 4;
+    float qx[kSlots], qy[kSlots], qz[kSlots], fx[kSlots], fy[kSlots], fz[kSlots];
+    int qi[kSlots];
+#pragma unroll
+    for (int m = 0; m < kSlots; ++m) {
+        const int i = seg + 16 * m;
+        const float4 q = xs[i < N ? i : N - 1];
+        qx[m] = q.x; qy[m] = q.y; qz[m] = q.z; qi[m] = info_of(q);
+        fx[m] = fy[m] = fz[m] = 0.0f;
+    }
     double t_ab = 0.0, t_bb = 0.0, t_bend = 0.0, t_tors = 0.0;
     for (int jb = 0; jb < N; jb += 4) {
         const int j = jb + row;
-        const int jj = j < N ? j : N - 1;
-        const float4 pj = xs[jj];
-        const int infj = info_of(pj);
+        const bool jl = j < N;
+        const float4 pj = xs[jl ? j : N - 1];
+        const int infj = info_of(pj), cj = bi_chain(infj), tj = bi_type(infj);
+        const int m0 = jb >> 4;
         float gx = 0.0f, gy = 0.0f, gz = 0.0f, sab = 0.0f, sbb = 0.0f;
-        for (int i = seg; i < N; i += 16) {
-            const float4 pi = xs[i];
-            const int infi = info_of(pi);
-            const bool use = j < N && !(bi_chain(infi) == bi_chain(infj) &&
-                                        (unsigned)(i - j + 1) <= 2u);
-            const float dx = mi_f(pj.x - pi.x, L, invL, per);
-            const float dy = mi_f(pj.y - pi.y, L, invL, per);
-            const float dz = mi_f(pj.z - pi.z, L, invL, per);
+#pragma unroll
+        for (int m = 0; m < kSlots; ++m) {
+            if (m < m0 || m >= nm) continue;
+            const int i = seg + 16 * m;
+            const bool same = bi_chain(qi[m]) == cj;
+            const bool use = jl && i > j && i < N && !(same && i == j + 1);
+            const float dx = sep<PERIODIC>(pj.x - qx[m], L, invL);
+            const float dy = sep<PERIODIC>(pj.y - qy[m], L, invL);
+            const float dz = sep<PERIODIC>(pj.z - qz[m], L, invL);
             const float r2 = use ? dx * dx + dy * dy + dz * dz : 1.0f;
             const float sr = __builtin_amdgcn_rcpf(r2);
             const float s3 = use ? sr * sr * sr : 0.0f;
-            const float4 k = coef[pair_slot(infi, infj)];
-            // d/dx_j of kappa (r^-12 - C r^-6) = (-12 kappa s^3 + 6 kappa C) s^3 s d, s = 1/r^2
+            const float4 k = coef[(same ? 0 : kMaxTypes * kMaxTypes) + bi_type(qi[m]) * kMaxTypes + tj];
+            // d/dx_j of kappa (r^-12 - C r^-6) = (-12 kappa s^3 + 6 kappa C) s^3 s d, s = 1/r^2;
+            // bead i gets the opposite force
             const float f = (k.x * s3 + k.y) * s3 * sr;
-            gx += f * dx;
-            gy += f * dy;
-            gz += f * dz;
+            gx += f * dx; gy += f * dy; gz += f * dz;
+            fx[m] -= f * dx; fy[m] -= f * dy; fz[m] -= f * dz;
             sab += k.z * s3;
             sbb += k.w * s3;
         }
         gx = row_sum_f(gx);
         gy = row_sum_f(gy);
         gz = row_sum_f(gz);
-        if (seg == 0 && j < N) gp[j] = make_float4(gx, gy, gz, 0.0f);
+        if (seg == 0 && jl) gp[j] = make_float4(gx, gy, gz, 0.0f);
         t_ab += (double)sab;
         t_bb += (double)sbb;
+    }
+    // forces on bead i = s + 16 m summed over the four rows, in a fixed order
+#pragma unroll
+    for (int m = 0; m < kSlots; ++m) {
+        if (m >= nm) continue;
+        float vx = fx[m], vy = fy[m], vz = fz[m];
+        vx += __shfl_xor(vx, 16); vy += __shfl_xor(vy, 16); vz += __shfl_xor(vz, 16);
+        vx += __shfl_xor(vx, 32); vy += __shfl_xor(vy, 32); vz += __shfl_xor(vz, 32);
+        const int i = seg + 16 * m;
+        if (row == 0 && i < N) gi[i] = make_float4(vx, vy, vz, 0.0f);
     }
     const float kb = (float)th.k_bend, kt = (float)th.k_tors;
     const float4 z4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -229,7 +262,9 @@ __global__ void __launch_bounds__(64 * kEWaves) k_energy_bwd(EnergyArgs a, Theta
         // bending term b moves bead b by -dp; term b-1: +dp - dq; term b-2: +dq.
         // torsion term b: -dp; term b-1: +dp; term b-2: -dq; term b-3: +dq.
         float4 g = gp[b];
-        float4 c = bp[b];
+        float4 c = gi[b];
+        g.x += c.x; g.y += c.y; g.z += c.z;
+        c = bp[b];
         g.x -= c.x; g.y -= c.y; g.z -= c.z;
         c = tp[b];
         g.x -= c.x; g.y -= c.y; g.z -= c.z;
@@ -252,8 +287,7 @@ __global__ void __launch_bounds__(64 * kEWaves) k_energy_bwd(EnergyArgs a, Theta
             out[2] = (float)(ge * (double)g.z);
         }
     }
-    // every unordered pair was visited from both ends
-    const double s_ab = 0.5 * wave_sum_d(t_ab), s_bb = 0.5 * wave_sum_d(t_bb);
+    const double s_ab = wave_sum_d(t_ab), s_bb = wave_sum_d(t_bb);
     const double s_bend = wave_sum_d(t_bend), s_tors = wave_sum_d(t_tors);
     if (live && lane == 0) {
         double *tpart = a.theta_part + cfg * 4;
@@ -296,8 +330,12 @@ hipError_t launch_energy_fwd(const EnergyArgs &a, hipStream_t st) {
     const Theta th = make_theta(a);
     const long long blocks = (a.n_cfg + kEWaves - 1) / kEWaves;
     const size_t lds = sizeof(float4) * (size_t)kEWaves * a.n_beads;
-    hipLaunchKernelGGL(k_energy_fwd, dim3((unsigned)blocks), dim3(64 * kEWaves), lds, st, a, th,
-                       a.n_beads);
+    if (a.periodic)
+        hipLaunchKernelGGL(k_energy_fwd<true>, dim3((unsigned)blocks), dim3(64 * kEWaves), lds, st,
+                           a, th, a.n_beads);
+    else
+        hipLaunchKernelGGL(k_energy_fwd<false>, dim3((unsigned)blocks), dim3(64 * kEWaves), lds, st,
+                           a, th, a.n_beads);
     return hipGetLastError();
 }
 
@@ -305,9 +343,13 @@ hipError_t launch_energy_bwd(const EnergyArgs &a, double *grad_theta, hipStream_
     if (a.n_beads < 3 || a.n_beads > kMaxBeads) return hipErrorInvalidValue;
     const Theta th = make_theta(a);
     const long long blocks = (a.n_cfg + kEWaves - 1) / kEWaves;
-    const size_t lds = sizeof(float4) * (size_t)kEWaves * 6 * a.n_beads;
-    hipLaunchKernelGGL(k_energy_bwd, dim3((unsigned)blocks), dim3(64 * kEWaves), lds, st, a, th,
-                       a.n_beads);
+    const size_t lds = sizeof(float4) * (size_t)kEWaves * 7 * a.n_beads;
+    if (a.periodic)
+        hipLaunchKernelGGL(k_energy_bwd<true>, dim3((unsigned)blocks), dim3(64 * kEWaves), lds, st,
+                           a, th, a.n_beads);
+    else
+        hipLaunchKernelGGL(k_energy_bwd<false>, dim3((unsigned)blocks), dim3(64 * kEWaves), lds, st,
+                           a, th, a.n_beads);
     hipLaunchKernelGGL(k_theta_sum, dim3(4), dim3(1024), 0, st, a.theta_part, a.n_cfg, grad_theta);
     return hipGetLastError();
 }
