@@ -185,9 +185,14 @@ PAPER_MAXWELL = {"cross_human": {"latent": 0.513, "barrier": 0.034},
                  "cross_rat": {"latent": 0.584, "barrier": 0.021}}
 
 
-def paper_physics_leg(stream, names, iters=1000, sweeps=2442, first=700, block=25):
-    """Full multicanonical runs of the paper's example systems as in Sec. 4: 4096 walkers share
-    about 10^7 sweeps per iteration (`sweeps` each), `iters` Berg iterations, then the
+# Sweeps per MUCA iteration, summed over all walkers, in the paper's runs (Sec. 4.1: 10^6 for the
+# dimer; Sec. 4.2: 10^7 for the cross-seeding mixtures).
+PAPER_SWEEPS_PER_ITERATION = {"abeta_dimer": 10 ** 6, "cross_human": 10 ** 7, "cross_rat": 10 ** 7}
+
+
+def paper_physics_leg(stream, names, iters=1000, walkers=4096, first=700, block=25):
+    """Full multicanonical runs of the paper's example systems as in Sec. 4: `walkers` walkers
+    share the paper's sweeps per iteration, `iters` Berg iterations, then the
     microcanonical analysis (Eqs. 4-8) of iterations [first, iters) in blocks of `block`:
     Maxwell construction on beta(eps), latent heat and free-energy barrier per monomer, and
     whether the caloric curve bends back (a region of negative microcanonical specific heat).
@@ -196,8 +201,9 @@ def paper_physics_leg(stream, names, iters=1000, sweeps=2442, first=700, block=2
     import workloads
     out = {}
     for name in names:
-        wl = workloads.paper_system(name)
+        wl = workloads.paper_system(name, walkers=walkers)
         sp = wl.systems[0]
+        sweeps = -(-PAPER_SWEEPS_PER_ITERATION[name] // walkers)
         m = P.Muca.from_workload(wl, workloads.initial_positions(wl),
                                  walkers=wl.walkers_per_system, stream=stream.cuda_stream)
         m.autotune(probe_sweeps=20)
@@ -213,6 +219,7 @@ def paper_physics_leg(stream, names, iters=1000, sweeps=2442, first=700, block=2
                       f"peak {st[2]:.3f} bins [{int(st[3])}, {int(st[4])}] "
                       f"{time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
         st = m.stats_history(0, iters)[:, 0]
+        h_last = m.histogram(0, last=True).astype(np.float64)
         m.close()
         flat = (st[:, 1] < 0.05) & (st[:, 2] < 0.20)
         conv = next((i for i in range(iters) if flat[i:].all()), None)
@@ -222,13 +229,16 @@ def paper_physics_leg(stream, names, iters=1000, sweeps=2442, first=700, block=2
             out[name] = {"error": f"visited range [{lo}, {hi}) too narrow to analyse",
                          "flat_iterations": int(flat.sum())}
             continue
+        inner = h_last[lo:hi]
+        inner_cvar = float(inner.std() / inner.mean()) if inner.mean() > 0 else None
         res = P.microcanonical_analyze(B, A, sp.e_lo, wl.bin_width, lo, hi, first, iters, block,
                                        5 * wl.bin_width, beta_c=0.0, tol_beta=1e-3, tol_l=0.02,
                                        n_monomers=sp.n_beads)
         dbeta = np.diff(res["beta"])
         rec = {"beads": sp.n_beads, "sphere_radius": wl.box_len, "iterations": iters,
                "sweeps_per_iteration": sweeps * wl.walkers_per_system,
-               "flat_iterations": int(flat.sum()), "flat_from": conv,
+               "walkers": walkers, "flat_iterations": int(flat.sum()), "flat_from": conv,
+               "last_cvar_full_range": float(st[-1, 1]), "last_cvar_analysed_range": inner_cvar,
                "eps_range": [float(res["E"][0]), float(res["E"][-1])],
                "beta_c": res["beta_c"], "dbeta_c": res["dbeta_c"],
                "latent_heat": res["latent"], "dlatent_heat": res["dlatent"],
@@ -431,6 +441,7 @@ def main():
     ap.add_argument("--paper-physics", default="",
                     help="comma-separated paper systems: only run their full MUCA + analysis")
     ap.add_argument("--physics-iters", type=int, default=1000)
+    ap.add_argument("--physics-walkers", type=int, default=4096)
     ap.add_argument("--diff-only", action="store_true",
                     help="run only the differentiation leg (profiling)")
     ap.add_argument("--diff-configs", type=int, default=1_000_000)
@@ -451,6 +462,7 @@ def main():
     if args.paper_physics:
         print(json.dumps({"paper_physics": paper_physics_leg(
             st, args.paper_physics.split(","), iters=args.physics_iters,
+            walkers=args.physics_walkers,
             first=int(0.7 * args.physics_iters), block=max(1, args.physics_iters // 40))}))
         return
     if args.diff_only:
