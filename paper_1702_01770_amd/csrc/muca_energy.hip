@@ -287,30 +287,65 @@ __global__ void __launch_bounds__(64 * kEWaves) k_energy_bwd(EnergyArgs a, Theta
             out[2] = (float)(ge * (double)g.z);
         }
     }
+    // grad_e * dE/dtheta of this configuration, summed over the workgroup's waves in order
+    __shared__ double wsum[kEWaves][4];
     const double s_ab = wave_sum_d(t_ab), s_bb = wave_sum_d(t_bb);
     const double s_bend = wave_sum_d(t_bend), s_tors = wave_sum_d(t_tors);
-    if (live && lane == 0) {
-        double *tpart = a.theta_part + cfg * 4;
-        tpart[0] = ge * s_ab; tpart[1] = ge * s_bb; tpart[2] = ge * s_bend; tpart[3] = ge * s_tors;
+    if (lane == 0) {
+        const double w = live ? ge : 0.0;
+        wsum[wave][0] = w * s_ab; wsum[wave][1] = w * s_bb;
+        wsum[wave][2] = w * s_bend; wsum[wave][3] = w * s_tors;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double v = 0.0;
+        for (int w = 0; w < kEWaves; ++w) v += wsum[w][threadIdx.x];
+        a.theta_part[(size_t)blockIdx.x * 4 + threadIdx.x] = v;
     }
 }
 
-// grad_theta[t] = sum over configurations of theta_part[cfg][t]; one workgroup per t, fixed
-// summation order.
-__global__ void __launch_bounds__(1024) k_theta_sum(const double *part, long long n, double *out) {
-    __shared__ double sh[16];
-    const int t = blockIdx.x;
-    double acc = 0.0;
-    for (long long c = threadIdx.x; c < n; c += blockDim.x) acc += part[c * 4 + t];
+// grad_theta = sum of the per-workgroup partials, in two fixed-order levels: k_theta_partial
+// sums contiguous chunks (one workgroup each), k_theta_final adds the chunk sums in order.
+constexpr int kThetaChunks = 256;
+
+// Sum of v[t] over the 256 threads for t = threadIdx.x < 4 (fixed order); other threads get 0.
+__device__ __forceinline__ double block_sum4(double v[4], double (*sh)[4]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    acc = wave_sum_d(acc);
-    if (lane == 0) sh[wave] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
-        out[t] = s;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const double s = wave_sum_d(v[t]);
+        if (lane == 0) sh[wave][t] = s;
     }
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x < 4)
+        for (int w = 0; w < 4; ++w) s += sh[w][threadIdx.x];
+    return s;
+}
+
+__global__ void __launch_bounds__(256) k_theta_partial(const double *part, long long n,
+                                                       long long chunk, double *out) {
+    __shared__ double sh[4][4];
+    const long long lo = (long long)blockIdx.x * chunk, hi = min(n, lo + chunk);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long c = lo + threadIdx.x; c < hi; c += blockDim.x)
+        for (int t = 0; t < 4; ++t) v[t] += part[c * 4 + t];
+    const double s = block_sum4(v, sh);
+    if (threadIdx.x < 4) out[(size_t)blockIdx.x * 4 + threadIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) k_theta_final(const double *part, int n, double *out) {
+    __shared__ double sh[4][4];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = threadIdx.x; c < n; c += blockDim.x)
+        for (int t = 0; t < 4; ++t) v[t] += part[c * 4 + t];
+    const double s = block_sum4(v, sh);
+    if (threadIdx.x < 4) out[threadIdx.x] = s;
+}
+
+size_t energy_bwd_scratch_doubles(long long n_cfg) {
+    const long long blocks = (n_cfg + kEWaves - 1) / kEWaves;
+    return 4 * (size_t)(blocks + kThetaChunks);
 }
 
 static Theta make_theta(const EnergyArgs &a) {
@@ -350,7 +385,12 @@ hipError_t launch_energy_bwd(const EnergyArgs &a, double *grad_theta, hipStream_
     else
         hipLaunchKernelGGL(k_energy_bwd<false>, dim3((unsigned)blocks), dim3(64 * kEWaves), lds, st,
                            a, th, a.n_beads);
-    hipLaunchKernelGGL(k_theta_sum, dim3(4), dim3(1024), 0, st, a.theta_part, a.n_cfg, grad_theta);
+    const long long chunk = (blocks + kThetaChunks - 1) / kThetaChunks;
+    const int n_chunks = (int)((blocks + chunk - 1) / chunk);
+    double *chunk_sums = a.theta_part + 4 * blocks;
+    hipLaunchKernelGGL(k_theta_partial, dim3(n_chunks), dim3(256), 0, st, a.theta_part, blocks,
+                       chunk, chunk_sums);
+    hipLaunchKernelGGL(k_theta_final, dim3(1), dim3(256), 0, st, chunk_sums, n_chunks, grad_theta);
     return hipGetLastError();
 }
 

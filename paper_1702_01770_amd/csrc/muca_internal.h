@@ -81,10 +81,12 @@ struct EnergyArgs {
     double *energy;            // [n_cfg]
     const double *grad_e;      // [n_cfg]
     float *grad_x;             // [n_cfg][N][3]
-    double *theta_part;        // [n_cfg][4] per-configuration grad_e * dE/dtheta
+    double *theta_part;        // scratch of energy_bwd_scratch_doubles(n_cfg) doubles: per-
+                               // workgroup grad_e * dE/dtheta partials, then chunk sums
 };
 hipError_t launch_energy_fwd(const EnergyArgs &a, hipStream_t st);
 hipError_t launch_energy_bwd(const EnergyArgs &a, double *grad_theta, hipStream_t st);
+size_t energy_bwd_scratch_doubles(long long n_cfg);
 
 // Reweighting (muca_reweight.hip).
 size_t reweight_workspace_bytes(long long n, int n_t);

@@ -972,12 +972,12 @@ int muca_energy_bwd(muca_ctx *ctx, int32_t sys, const float *x, int64_t n_cfg,
     if (!grad_e || !grad_x || !grad_theta) return fail(ctx, MUCA_E_INVAL, "null gradient pointer");
     if (n_cfg == 0) return MUCA_OK;
     if (n_cfg > ctx->theta_part_cap) {
-        // per-configuration dE/dtheta partials, kept for later calls
+        // dE/dtheta partials and chunk sums, kept for later calls
         CK(hipStreamSynchronize(ctx->stream));
         if (ctx->d_theta_part) CK(hipFree(ctx->d_theta_part));
         ctx->d_theta_part = nullptr;
         ctx->theta_part_cap = 0;
-        CK(hipMalloc(&ctx->d_theta_part, sizeof(double) * 4 * (size_t)n_cfg));
+        CK(hipMalloc(&ctx->d_theta_part, sizeof(double) * energy_bwd_scratch_doubles(n_cfg)));
         ctx->theta_part_cap = n_cfg;
     }
     a.grad_e = grad_e;
