@@ -217,8 +217,9 @@ int muca_get_launch_info(muca_ctx *ctx, muca_launch_info *out);
  * Energy and its gradients for stored configurations of system sys (differentiation of
  * reweighted averages; not part of the paper).  theta = (C_AB, C_BB, k_bend, k_tors) replaces
  * the corresponding couplings (two-letter lexicon, C_AA and the LJ prefactors from the
- * context).  x: device FP32 [n_cfg][N][3]; energy: device FP64 [n_cfg].  Pair terms in FP32,
- * sums in FP64.  Enqueued on the context stream.
+ * context).  x: device FP32 [n_cfg][N][3]; energy: device FP64 [n_cfg].  Pair terms and the
+ * per-bead force sums in FP32; energies and dE/dtheta summed in FP64; every sum in a fixed
+ * order, so repeated calls give identical results.  Enqueued on the context stream.
  */
 int muca_energy_fwd(muca_ctx *ctx, int32_t sys, const float *x, int64_t n_cfg,
                     const double theta[4], double *energy);
