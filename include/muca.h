@@ -138,6 +138,7 @@ typedef struct {
     double max_drift;                     /* largest |E_running - E_full| seen at a resync */
     uint64_t pivot_moves, pivot_accepted; /* pivots */
     uint64_t rot_moves, rot_accepted;     /* rigid chain rotations */
+    uint64_t hmc_trajectories, hmc_accepted; /* hybrid Monte Carlo trajectories (muca_hmc) */
 } muca_walker_counters;
 
 /* Create a context: validates cfg, copies everything to the device, computes every walker's
@@ -160,6 +161,20 @@ int muca_sweep(muca_ctx *ctx, int64_t n_sweeps);
  * temperature range; bins below the lowest visited one copy its clamped slope).  Synchronises
  * the stream.  stats: host [n_systems] or NULL. */
 int muca_update_weights(muca_ctx *ctx, muca_iter_stats *stats);
+
+/* Hybrid Monte Carlo (the hybrid MCMC the paper plans, Sec. 5): enqueue n_traj trajectories
+ * of every walker under the current weights on the context stream (asynchronous).  A chain is
+ * its first bead plus unit bond vectors; the first bead moves as a free particle, every bond
+ * along its great circle (geodesic leapfrog: n_steps steps of length step), under the forces
+ * -beta(E) dE/dx of U = -ln W(E) (Eq. 8, beta the slope of -ln W in the bin of E).  Momenta:
+ * Box-Muller normals from Philox blocks (bead j, lo32(T), hi32(T), 7) of the walker's key, T
+ * the walker's trajectory count; acceptance: ln u < H_old - H_new with u from block
+ * (0, lo32(T), hi32(T), 8), H = -ln W(E) + |p|^2 / 2; an end outside the window or the
+ * sphere rejects.  One histogram count per trajectory at the energy after the decision (added
+ * to the running histogram the weight update reads).  Energies and forces in FP64 in both
+ * precision modes.  At most 64 beads per system (MUCA_E_INVAL otherwise); n_steps >= 1,
+ * step > 0. */
+int muca_hmc(muca_ctx *ctx, int64_t n_traj, int32_t n_steps, double step);
 
 /* Enqueue n_iter iterations of (n_sweeps sweeps + weight update) without host round trips; the
  * statistics are kept on the device (read them with muca_get_stats_history). */

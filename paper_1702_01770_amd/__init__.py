@@ -119,6 +119,11 @@ class Muca:
     def sweep(self, n_sweeps: int):
         self._ck(self._L.muca_sweep(self._h, int(n_sweeps)))
 
+    def hmc(self, n_traj: int, n_steps: int, step: float):
+        """n_traj hybrid Monte Carlo trajectories of every walker (n_steps leapfrog steps of
+        length step) under the current weights; one histogram count per trajectory."""
+        self._ck(self._L.muca_hmc(self._h, int(n_traj), int(n_steps), float(step)))
+
     def update_weights(self):
         st = (_lib.IterStats * self.n_systems)()
         self._ck(self._L.muca_update_weights(self._h, st))

@@ -41,7 +41,8 @@ class WalkerCounters(C.Structure):
                 ("rigid_accepted", C.c_uint64), ("window_rejects", C.c_uint64),
                 ("sweeps", C.c_uint64), ("max_drift", C.c_double),
                 ("pivot_moves", C.c_uint64), ("pivot_accepted", C.c_uint64),
-                ("rot_moves", C.c_uint64), ("rot_accepted", C.c_uint64)]
+                ("rot_moves", C.c_uint64), ("rot_accepted", C.c_uint64),
+                ("hmc_trajectories", C.c_uint64), ("hmc_accepted", C.c_uint64)]
 
 
 class LaunchInfo(C.Structure):
@@ -70,7 +71,7 @@ class AnalysisOut(C.Structure):
                 ("n_blocks", C.c_int32)]
 
 
-EXPORTS = ["muca_init", "muca_sweep", "muca_update_weights", "muca_iterate",
+EXPORTS = ["muca_init", "muca_sweep", "muca_hmc", "muca_update_weights", "muca_iterate",
            "muca_get_stats_history", "muca_synchronize", "muca_get_histogram",
            "muca_get_weights", "muca_set_weights", "muca_get_walkers", "muca_set_walkers",
            "muca_set_accept_log", "muca_get_accept_log", "muca_get_state", "muca_set_state",
@@ -100,6 +101,7 @@ def load():
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     L.muca_init.argtypes = [C.POINTER(MucaConfig), C.POINTER(vp)]
     L.muca_sweep.argtypes = [vp, i64]
+    L.muca_hmc.argtypes = [vp, i64, i32, C.c_double]
     L.muca_update_weights.argtypes = [vp, C.POINTER(IterStats)]
     L.muca_iterate.argtypes = [vp, i64, i32]
     L.muca_get_stats_history.argtypes = [vp, i64, i32, C.POINTER(IterStats)]

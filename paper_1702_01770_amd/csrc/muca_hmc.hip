@@ -1,0 +1,263 @@
+// Hybrid Monte Carlo under the multicanonical weights (the hybrid MCMC the paper plans, Sec. 5).
+//
+// A chain is its first bead o_c plus unit bond vectors u_j = x_j - x_{j-1} (indexed by the bead
+// j that ends the bond), so the rigid bonds need no constraint forces: origins move as free
+// particles and every bond along its great circle (geodesic leapfrog).  The potential is
+// U = -ln W(E) (Eq. 8), so the bead forces are -beta(E) dE/dx with beta the slope of -ln W in
+// the bin of the current energy; the force on the vector of bead j is the sum of the bead forces
+// of the beads i >= j of its chain.  Metropolis on H = U + |p|^2 / 2 keeps pi ~ W(E) with
+// respect to the freely-jointed reference measure that the single-bead moves sample.
+//
+// One wave per walker, lane j holds bead j (at most 64 beads): position, vector, momentum.
+// Positions are segmented prefix sums of the vectors and generalized forces segmented suffix
+// sums of the bead forces (shuffle scans within each chain); energies and forces in FP64, the
+// pair loop over all beads per lane, angle terms once per lane and gathered through LDS.
+#include "muca_internal.h"
+
+namespace muca {
+
+constexpr int kHmcWaves = 4;   // walkers per workgroup
+
+struct HmcLds {
+    double x[64], y[64], z[64];
+    double bp[64][3], bq[64][3], tp[64][3], tq[64][3];
+};
+
+__device__ __forceinline__ double seg_prefix(double v, int lane, int cs) {
+    for (int d = 1; d < 64; d <<= 1) {
+        const double y = __shfl_up(v, d);
+        if (lane - d >= cs) v += y;
+    }
+    return v;
+}
+
+__device__ __forceinline__ double seg_suffix(double v, int lane, int ce) {
+    for (int d = 1; d < 64; d <<= 1) {
+        const double y = __shfl_down(v, d);
+        if (lane + d <= ce) v += y;
+    }
+    return v;
+}
+
+// Derivative of kappa (1 - p.q / (|p||q|)) with respect to the bonds p and q; returns 1 - cos.
+__device__ __forceinline__ double angle_grad(const double p[3], const double q[3], double kappa,
+                                             double dp[3], double dq[3]) {
+    const double np = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    const double nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+    double u[3], v[3];
+    for (int c = 0; c < 3; ++c) { u[c] = p[c] / np; v[c] = q[c] / nq; }
+    const double cs = u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+    for (int c = 0; c < 3; ++c) {
+        dp[c] = -kappa * (v[c] - cs * u[c]) / np;
+        dq[c] = -kappa * (u[c] - cs * v[c]) / nq;
+    }
+    return 1.0 - cs;
+}
+
+// Energy (wave-uniform) and this lane's dE/dx for the positions in L.
+template <bool PERIODIC>
+__device__ double energy_forces(const SweepArgs &a, HmcLds &L, const int *bi, int N, int lane,
+                                int ce, double &gx, double &gy, double &gz) {
+    const bool act = lane < N;
+    double e = 0.0;
+    gx = gy = gz = 0.0;
+    const double xj = L.x[act ? lane : 0], yj = L.y[act ? lane : 0], zj = L.z[act ? lane : 0];
+    if (act) {
+        const int infj = bi[lane], tj = bi_type(infj), cj = bi_chain(infj);
+        for (int i = 0; i < N; ++i) {
+            const int infi = bi[i];
+            const bool same = bi_chain(infi) == cj;
+            if (i == lane || (same && (i == lane - 1 || i == lane + 1))) continue;
+            double dx = xj - L.x[i], dy = yj - L.y[i], dz = zj - L.z[i];
+            if constexpr (PERIODIC) {
+                dx -= a.box_len * rint(dx * a.inv_box);
+                dy -= a.box_len * rint(dy * a.inv_box);
+                dz -= a.box_len * rint(dz * a.inv_box);
+            }
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double s = 1.0 / r2, s3 = s * s * s;
+            const double kap = same ? a.k_intra : a.k_inter;
+            const double cc = a.c_lj[tj * a.n_types + bi_type(infi)];
+            e += 0.5 * kap * s3 * (s3 - cc);
+            const double f = kap * (-12.0 * s3 + 6.0 * cc) * s3 * s;
+            gx += f * dx; gy += f * dy; gz += f * dz;
+        }
+    }
+    // bending (beads j, j+1, j+2) and torsion-like (j .. j+3) terms of this lane
+    double dp[3] = {0, 0, 0}, dq[3] = {0, 0, 0}, ep[3] = {0, 0, 0}, eq[3] = {0, 0, 0};
+    if (act && lane + 2 <= ce) {
+        const double p[3] = {L.x[lane + 1] - xj, L.y[lane + 1] - yj, L.z[lane + 1] - zj};
+        const double q[3] = {L.x[lane + 2] - L.x[lane + 1], L.y[lane + 2] - L.y[lane + 1],
+                             L.z[lane + 2] - L.z[lane + 1]};
+        e += a.k_bend * angle_grad(p, q, a.k_bend, dp, dq);
+    }
+    if (act && lane + 3 <= ce) {
+        const double p[3] = {L.x[lane + 1] - xj, L.y[lane + 1] - yj, L.z[lane + 1] - zj};
+        const double q[3] = {L.x[lane + 3] - L.x[lane + 2], L.y[lane + 3] - L.y[lane + 2],
+                             L.z[lane + 3] - L.z[lane + 2]};
+        e += a.k_tors * angle_grad(p, q, a.k_tors, ep, eq);
+    }
+    for (int c = 0; c < 3; ++c) {
+        L.bp[lane][c] = dp[c]; L.bq[lane][c] = dq[c];
+        L.tp[lane][c] = ep[c]; L.tq[lane][c] = eq[c];
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (act) {
+        // bending term b moves bead b by -dp, term b-1 by dp - dq, term b-2 by dq; torsion term
+        // b: -dp, b-1: +dp, b-2: -dq, b-3: +dq
+        double g[3] = {gx, gy, gz};
+        for (int c = 0; c < 3; ++c) {
+            g[c] -= L.bp[lane][c] + L.tp[lane][c];
+            if (lane >= 1) g[c] += L.bp[lane - 1][c] - L.bq[lane - 1][c] + L.tp[lane - 1][c];
+            if (lane >= 2) g[c] += L.bq[lane - 2][c] - L.tq[lane - 2][c];
+            if (lane >= 3) g[c] += L.tq[lane - 3][c];
+        }
+        gx = g[0]; gy = g[1]; gz = g[2];
+    }
+    __builtin_amdgcn_wave_barrier();   // the arrays are rewritten by the next evaluation
+    return wave_sum_d(e);
+}
+
+// Bin of e, edge bins extended (a non-finite energy maps to bin 0; such an end is rejected).
+__device__ __forceinline__ int bin_of(double e, double e_lo, double eps, int K) {
+    const double t = floor((e - e_lo) / eps);
+    if (!(t >= 0.0)) return 0;
+    return t >= (double)K ? K - 1 : (int)t;
+}
+
+template <bool PERIODIC>
+__global__ void __launch_bounds__(64 * kHmcWaves) k_hmc(SweepArgs a, HmcArgs h) {
+    __shared__ HmcLds lds[kHmcWaves];
+    __shared__ int bis[kHmcWaves][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = blockIdx.x * kHmcWaves + wave;
+    if (w >= h.n_walkers) return;                 // no workgroup barrier below
+    HmcLds &L = lds[wave];
+    int *bi = bis[wave];
+    const int sys = h.walker_sys[w];
+    const SysDev &sd = a.sys[sys];
+    const int N = sd.n_beads, K = sd.n_bins;
+    const bool act = lane < N;
+    const int inf = act ? a.binfo[sys * kMaxBeads + lane] : bead_info(0, 255, true, true);
+    bi[lane] = inf;
+    const bool first = bi_first(inf);
+    const int cs = act ? sd.chain_start[bi_chain(inf)] : lane;
+    const int ce = act ? sd.chain_start[bi_chain(inf) + 1] - 1 : lane;
+    const double e_lo = sd.e_lo, eps = a.bin_width;
+    const double *beta = a.beta + sd.bin_off, *alpha = a.alpha + sd.bin_off;
+    double *P = a.pos + (size_t)w * 3 * a.npad;
+    double x = act ? P[lane] : 0.0, y = act ? P[a.npad + lane] : 0.0, z = act ? P[2 * a.npad + lane] : 0.0;
+    double E = a.energy[w];
+    unsigned long long *hc = h.cnt + (size_t)w * 2;
+    unsigned long long T = hc[0];
+    const unsigned int k0 = a.seed_lo, k1 = a.seed_hi ^ (unsigned int)w;
+    unsigned long long n_acc = 0, n_wrej = 0;
+    const double hs = h.step;
+
+    for (long long tr = 0; tr < h.n_traj; ++tr, ++T) {
+        L.x[lane] = x; L.y[lane] = y; L.z[lane] = z;
+        __builtin_amdgcn_wave_barrier();
+        // vectors: the first bead's position, else the bond ending at this bead
+        double vx = x, vy = y, vz = z;
+        if (act && !first) { vx = x - L.x[lane - 1]; vy = y - L.y[lane - 1]; vz = z - L.z[lane - 1]; }
+        // momenta
+        const U4 r = philox4x32_10((unsigned)lane, (unsigned)T, (unsigned)(T >> 32), 7u, k0, k1);
+        const double a0 = u01(r.x), a1 = u01(r.y), a2 = u01(r.z), a3 = u01(r.w);
+        const double r0 = sqrt(-2.0 * log(a0)), r2 = sqrt(-2.0 * log(a2));
+        double mx = r0 * cos(2.0 * M_PI * a1), my = r0 * sin(2.0 * M_PI * a1), mz = r2 * cos(2.0 * M_PI * a3);
+        if (!first) {
+            const double d = mx * vx + my * vy + mz * vz;
+            mx -= d * vx; my -= d * vy; mz -= d * vz;
+        }
+        if (!act) { mx = my = mz = 0.0; vx = vy = vz = 0.0; }
+        const double H0 = -(-beta[bin_of(E, e_lo, eps, K)] * E + alpha[bin_of(E, e_lo, eps, K)]) +
+                          0.5 * wave_sum_d(mx * mx + my * my + mz * mz);
+        // forces at the start
+        double gx, gy, gz;
+        double Ec = energy_forces<PERIODIC>(a, L, bi, N, lane, ce, gx, gy, gz);
+        auto gen_forces = [&](double Ecur, double &Gx, double &Gy, double &Gz) {
+            const double b = beta[bin_of(Ecur, e_lo, eps, K)];
+            Gx = seg_suffix(-b * gx, lane, ce);
+            Gy = seg_suffix(-b * gy, lane, ce);
+            Gz = seg_suffix(-b * gz, lane, ce);
+        };
+        double Gx, Gy, Gz;
+        gen_forces(Ec, Gx, Gy, Gz);
+        auto kick = [&](double hh) {
+            double tx = Gx, ty = Gy, tz = Gz;
+            if (!first) {
+                const double d = Gx * vx + Gy * vy + Gz * vz;
+                tx -= d * vx; ty -= d * vy; tz -= d * vz;
+            }
+            if (act) { mx += hh * tx; my += hh * ty; mz += hh * tz; }
+        };
+        double nx = x, ny = y, nz = z;
+        for (int st = 0; st < h.n_steps; ++st) {
+            kick(0.5 * hs);
+            if (act) {
+                if (first) {
+                    vx += hs * mx; vy += hs * my; vz += hs * mz;
+                } else {
+                    const double sp = sqrt(mx * mx + my * my + mz * mz);
+                    const double c = cos(sp * hs), s = sin(sp * hs);
+                    const double safe = sp > 0.0 ? sp : 1.0;
+                    double ux = vx * c + (mx / safe) * s, uy = vy * c + (my / safe) * s,
+                           uz = vz * c + (mz / safe) * s;
+                    double wx = mx * c - vx * (sp * s), wy = my * c - vy * (sp * s),
+                           wz = mz * c - vz * (sp * s);
+                    const double nu = sqrt(ux * ux + uy * uy + uz * uz);
+                    ux /= nu; uy /= nu; uz /= nu;
+                    const double d = wx * ux + wy * uy + wz * uz;
+                    wx -= d * ux; wy -= d * uy; wz -= d * uz;
+                    vx = ux; vy = uy; vz = uz; mx = wx; my = wy; mz = wz;
+                }
+            }
+            nx = seg_prefix(vx, lane, cs);
+            ny = seg_prefix(vy, lane, cs);
+            nz = seg_prefix(vz, lane, cs);
+            L.x[lane] = nx; L.y[lane] = ny; L.z[lane] = nz;
+            __builtin_amdgcn_wave_barrier();
+            Ec = energy_forces<PERIODIC>(a, L, bi, N, lane, ce, gx, gy, gz);
+            gen_forces(Ec, Gx, Gy, Gz);
+            kick(0.5 * hs);
+        }
+        const double t1 = (Ec - e_lo) / eps;
+        const bool inwin = t1 >= 0.0 && t1 < (double)K;
+        const bool out = act && a.sphere_r2 > 0.0 && nx * nx + ny * ny + nz * nz > a.sphere_r2;
+        const bool inside = __ballot(out) == 0;
+        const double K1 = 0.5 * wave_sum_d(mx * mx + my * my + mz * mz);
+        const int k1b = bin_of(Ec, e_lo, eps, K);
+        const double H1 = -(-beta[k1b] * Ec + alpha[k1b]) + K1;
+        const U4 ra = philox4x32_10(0u, (unsigned)T, (unsigned)(T >> 32), 8u, k0, k1);
+        const bool accept = inwin && inside && (log(u01(ra.x)) < H0 - H1);
+        n_wrej += inwin ? 0 : 1;
+        if (accept) {
+            x = nx; y = ny; z = nz;
+            E = Ec;
+            ++n_acc;
+        }
+        if (lane == 0) {
+            atomicAdd(&a.hist[sd.bin_off + bin_of(E, e_lo, eps, K)], 1ull);
+        }
+        __builtin_amdgcn_wave_barrier();   // L.x is rewritten by the next trajectory
+    }
+    if (act) { P[lane] = x; P[a.npad + lane] = y; P[2 * a.npad + lane] = z; }
+    if (lane == 0) {
+        a.energy[w] = E;
+        hc[0] = T;
+        hc[1] += n_acc;
+        a.cnt[(size_t)w * C_NCOUNT + C_WREJ] += n_wrej;
+    }
+}
+
+hipError_t launch_hmc(const SweepArgs &a, const HmcArgs &h, bool periodic, hipStream_t st) {
+    if (h.n_walkers < 1 || h.n_steps < 1 || !(h.step > 0.0)) return hipErrorInvalidValue;
+    const int blocks = (h.n_walkers + kHmcWaves - 1) / kHmcWaves;
+    if (periodic)
+        hipLaunchKernelGGL(k_hmc<true>, dim3(blocks), dim3(64 * kHmcWaves), 0, st, a, h);
+    else
+        hipLaunchKernelGGL(k_hmc<false>, dim3(blocks), dim3(64 * kHmcWaves), 0, st, a, h);
+    return hipGetLastError();
+}
+
+}  // namespace muca

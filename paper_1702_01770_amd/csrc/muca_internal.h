@@ -24,6 +24,16 @@ hipError_t launch_sweep_pair_chain(const SweepArgs &a, bool fp64, int group, int
                                    bool periodic, int n_items, int waves_per_block,
                                    size_t lds_bytes, long long n_sweeps, int pos_stride,
                                    hipStream_t st);
+// Hybrid Monte Carlo trajectories (muca_hmc.hip): one wave per walker, at most 64 beads.
+struct HmcArgs {
+    const int *walker_sys;          // system of every walker
+    unsigned long long *cnt;        // [walkers][2]: trajectories done (the stream position), accepted
+    long long n_traj;               // trajectories per walker in this launch
+    int n_steps;                    // leapfrog steps per trajectory
+    double step;                    // leapfrog step
+    int n_walkers;
+};
+hipError_t launch_hmc(const SweepArgs &a, const HmcArgs &h, bool periodic, hipStream_t st);
 hipError_t launch_walker_energy(const SweepArgs &a, int slots, bool periodic, int n_walkers,
                                 const int *walker_sys, hipStream_t st);
 

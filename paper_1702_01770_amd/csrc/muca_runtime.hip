@@ -47,6 +47,7 @@ struct muca_ctx {
     WorkItem *d_work = nullptr;
     int *d_binfo = nullptr, *d_err = nullptr, *d_walker_sys = nullptr;
     double *d_pos = nullptr, *d_energy = nullptr, *d_drift = nullptr;
+    unsigned long long *d_hmc = nullptr;     // [walkers][2] hybrid MC trajectories, accepted
     unsigned long long *d_cnt = nullptr, *d_hist = nullptr, *d_hist_last = nullptr;
     double *d_beta = nullptr, *d_alpha = nullptr, *d_g = nullptr;
     unsigned int *d_acclog = nullptr;
@@ -346,7 +347,7 @@ void muca_destroy(muca_ctx *ctx) {
     void *ptrs[] = {ctx->d_sys, ctx->d_work, ctx->d_binfo, ctx->d_err, ctx->d_walker_sys,
                     ctx->d_pos, ctx->d_energy, ctx->d_drift, ctx->d_cnt, ctx->d_hist,
                     ctx->d_hist_last, ctx->d_beta, ctx->d_alpha, ctx->d_g, ctx->d_acclog,
-                    ctx->d_iter, ctx->d_stats, ctx->d_theta_part};
+                    ctx->d_iter, ctx->d_stats, ctx->d_theta_part, ctx->d_hmc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -528,6 +529,7 @@ int muca_init(const muca_config *cfg, muca_ctx **out) {
     ALLOC(ctx->d_energy, sizeof(double) * ctx->W_total);
     ALLOC(ctx->d_drift, sizeof(double) * ctx->W_total);
     ALLOC(ctx->d_cnt, sizeof(unsigned long long) * C_NCOUNT * ctx->W_total);
+    ALLOC(ctx->d_hmc, sizeof(unsigned long long) * 2 * ctx->W_total);
     ALLOC(ctx->d_hist, sizeof(unsigned long long) * ctx->total_bins);
     ALLOC(ctx->d_hist_last, sizeof(unsigned long long) * ctx->total_bins);
     ALLOC(ctx->d_beta, sizeof(double) * ctx->total_bins);
@@ -551,6 +553,7 @@ int muca_init(const muca_config *cfg, muca_ctx **out) {
     up(ctx->d_pos, pos.data(), sizeof(double) * pos.size());
     up(ctx->d_drift, zeros_d.data(), sizeof(double) * ctx->W_total);
     up(ctx->d_cnt, zeros_u.data(), sizeof(unsigned long long) * C_NCOUNT * ctx->W_total);
+    up(ctx->d_hmc, zeros_u.data(), sizeof(unsigned long long) * 2 * ctx->W_total);
     up(ctx->d_hist, zeros_u.data(), sizeof(unsigned long long) * ctx->total_bins);
     up(ctx->d_hist_last, zeros_u.data(), sizeof(unsigned long long) * ctx->total_bins);
     up(ctx->d_beta, zeros_d.data(), sizeof(double) * ctx->total_bins);
@@ -643,6 +646,23 @@ int muca_sweep(muca_ctx *ctx, int64_t n_sweeps) {
     int rc = get_graph(ctx, n_sweeps, false, &ex);
     if (rc != MUCA_OK) return rc;
     CK(hipGraphLaunch(ex, ctx->stream));
+    return MUCA_OK;
+}
+
+int muca_hmc(muca_ctx *ctx, int64_t n_traj, int32_t n_steps, double step) {
+    if (!ctx) return fail(nullptr, MUCA_E_INVAL, "null context");
+    if (n_traj < 0 || n_steps < 1 || !(step > 0.0) || !std::isfinite(step))
+        return fail(ctx, MUCA_E_INVAL, "hybrid MC needs n_traj >= 0, n_steps >= 1 and a positive step");
+    if (ctx->max_beads > 64) return fail(ctx, MUCA_E_INVAL, "hybrid MC supports at most 64 beads per system");
+    if (n_traj == 0) return MUCA_OK;
+    HmcArgs h{};
+    h.walker_sys = ctx->d_walker_sys;
+    h.cnt = ctx->d_hmc;
+    h.n_traj = n_traj;
+    h.n_steps = n_steps;
+    h.step = step;
+    h.n_walkers = ctx->W_total;
+    CK(launch_hmc(ctx->args, h, ctx->periodic, ctx->stream));
     return MUCA_OK;
 }
 
@@ -769,6 +789,9 @@ int muca_get_walkers(muca_ctx *ctx, int32_t sys, double *pos, double *energy,
         CK(hipMemcpy(c.data(), ctx->d_cnt + (size_t)h.walker_off * C_NCOUNT,
                      sizeof(unsigned long long) * c.size(), hipMemcpyDeviceToHost));
         CK(hipMemcpy(dr.data(), ctx->d_drift + h.walker_off, sizeof(double) * W, hipMemcpyDeviceToHost));
+        std::vector<unsigned long long> hm((size_t)W * 2);
+        CK(hipMemcpy(hm.data(), ctx->d_hmc + (size_t)h.walker_off * 2,
+                     sizeof(unsigned long long) * hm.size(), hipMemcpyDeviceToHost));
         for (int w = 0; w < W; ++w) {
             const unsigned long long *cw = c.data() + (size_t)w * C_NCOUNT;
             counters[w].moves = cw[C_MOVES];
@@ -782,6 +805,8 @@ int muca_get_walkers(muca_ctx *ctx, int32_t sys, double *pos, double *energy,
             counters[w].pivot_accepted = cw[C_PIVOT_ACC];
             counters[w].rot_moves = cw[C_ROT];
             counters[w].rot_accepted = cw[C_ROT_ACC];
+            counters[w].hmc_trajectories = hm[2 * (size_t)w];
+            counters[w].hmc_accepted = hm[2 * (size_t)w + 1];
         }
     }
     return MUCA_OK;
@@ -860,7 +885,7 @@ static const uint64_t kMagic = 0x4d55434153544154ull;   // "MUCASTAT"
 static size_t state_bytes(const muca_ctx *ctx) {
     const size_t nw = ctx->W_total, nb = ctx->total_bins;
     return sizeof(StateHeader) + sizeof(double) * (nw * 3 * ctx->npad + 2 * nw + 3 * nb) +
-           sizeof(unsigned long long) * (nw * C_NCOUNT + 2 * nb) + sizeof(long long);
+           sizeof(unsigned long long) * (nw * C_NCOUNT + 2 * nw + 2 * nb) + sizeof(long long);
 }
 
 int muca_get_state(muca_ctx *ctx, void *buf, size_t *bytes) {
@@ -872,7 +897,7 @@ int muca_get_state(muca_ctx *ctx, void *buf, size_t *bytes) {
     if (rc != MUCA_OK) return rc;
     const size_t nw = ctx->W_total, nb = ctx->total_bins;
     char *p = (char *)buf;
-    StateHeader h{kMagic, 1, nw * 3 * ctx->npad, nw, nb, nw * C_NCOUNT};
+    StateHeader h{kMagic, 2, nw * 3 * ctx->npad, nw, nb, nw * C_NCOUNT};
     std::memcpy(p, &h, sizeof h);
     p += sizeof h;
     auto get = [&](const void *src, size_t n) -> hipError_t {
@@ -887,6 +912,7 @@ int muca_get_state(muca_ctx *ctx, void *buf, size_t *bytes) {
     CK(get(ctx->d_alpha, sizeof(double) * nb));
     CK(get(ctx->d_g, sizeof(double) * nb));
     CK(get(ctx->d_cnt, sizeof(unsigned long long) * h.n_cnt));
+    CK(get(ctx->d_hmc, sizeof(unsigned long long) * 2 * nw));
     CK(get(ctx->d_hist, sizeof(unsigned long long) * nb));
     CK(get(ctx->d_hist_last, sizeof(unsigned long long) * nb));
     CK(get(ctx->d_iter, sizeof(long long)));
@@ -902,7 +928,7 @@ int muca_set_state(muca_ctx *ctx, const void *buf, size_t bytes) {
     StateHeader h;
     std::memcpy(&h, p, sizeof h);
     p += sizeof h;
-    if (h.magic != kMagic || h.version != 1 || h.n_walkers != nw || h.n_bins != nb ||
+    if (h.magic != kMagic || h.version != 2 || h.n_walkers != nw || h.n_bins != nb ||
         h.n_pos != nw * 3 * ctx->npad || h.n_cnt != nw * C_NCOUNT)
         return fail(ctx, MUCA_E_STATE, "state header does not match this context");
     CK(hipStreamSynchronize(ctx->stream));
@@ -918,6 +944,7 @@ int muca_set_state(muca_ctx *ctx, const void *buf, size_t bytes) {
     CK(put(ctx->d_alpha, sizeof(double) * nb));
     CK(put(ctx->d_g, sizeof(double) * nb));
     CK(put(ctx->d_cnt, sizeof(unsigned long long) * h.n_cnt));
+    CK(put(ctx->d_hmc, sizeof(unsigned long long) * 2 * nw));
     CK(put(ctx->d_hist, sizeof(unsigned long long) * nb));
     CK(put(ctx->d_hist_last, sizeof(unsigned long long) * nb));
     CK(put(ctx->d_iter, sizeof(long long)));
