@@ -252,6 +252,56 @@ def paper_physics_leg(stream, names, iters=1000, walkers=4096, first=700, block=
     return out
 
 
+def hmc_flops_per_step(chain_len, periodic=False):
+    """Operations one leapfrog step of one walker must perform: every unordered non-bonded pair
+    once (separation 3, +9 periodic, r^2 5, reciprocal 1, s^3 2, pair energy 3, force scalar 4,
+    force vector 3, added to both beads 6), every bending / torsion term once (value and bond
+    derivatives 49, scattered to its beads 9), and per bead the two half kicks with the tangent
+    projection (2 x 9), the drift (great-circle turn with cosine and sine, renormalisation and
+    projection: 30) and the position and force scans (2 x 3 x 6)."""
+    n = int(np.sum(chain_len))
+    m = len(chain_len)
+    pairs = n * (n - 1) // 2 - (n - m)
+    angles = sum(max(0, L - 2) for L in chain_len) + sum(max(0, L - 3) for L in chain_len)
+    return pairs * (27 + (9 if periodic else 0)) + angles * 58 + n * (18 + 30 + 36)
+
+
+def hmc_leg(stream, n_traj=10, n_steps=10, step=0.01):
+    """Hybrid Monte Carlo on the batched workload (4096 walkers, 32 single chains of 13..55
+    beads) under the weights of one 2000-sweep MUCA iteration: trajectories, leapfrog steps and
+    algorithmic FP64 operations per second, timed with HIP events on the library's stream."""
+    import torch
+
+    import paper_1702_01770_amd as P
+    import workloads
+    wl = workloads.batched_chains()
+    m = P.Muca.from_workload(wl, workloads.initial_positions(wl), stream=stream.cuda_stream)
+    m.iterate(2000, 1)
+    m.hmc(1, n_steps, step)                     # warm-up
+    m.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    m.hmc(n_traj, n_steps, step)
+    e1.record(stream)
+    e1.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    W = wl.walkers_per_system
+    acc = tot = 0
+    for s in range(len(wl.systems)):
+        _, _, c = m.walkers_state(s)
+        acc += int(np.sum(c["hmc_accepted"]))
+        tot += int(np.sum(c["hmc_trajectories"]))
+    m.close()
+    trajs = W * len(wl.systems) * n_traj
+    flops = W * n_traj * n_steps * sum(hmc_flops_per_step(sp.chain_len) for sp in wl.systems)
+    return {"walkers": W * len(wl.systems), "trajectories_per_walker": n_traj,
+            "leapfrog_steps": n_steps, "step": step, "ms": sec * 1e3,
+            "trajectories_per_s": trajs / sec, "leapfrog_steps_per_s": trajs * n_steps / sec,
+            "acceptance": acc / max(1, tot), "fp64_tflops": flops / sec / 1e12,
+            "fp64_peak_tflops": 78.6}
+
+
 def differentiation_flops_per_config(chain_len, periodic=True):
     """Operations the energy forward + backward must perform for one stored configuration, each
     unordered non-bonded pair once (Newton's third law) and each bending / torsion term once.
@@ -438,6 +488,7 @@ def main():
     ap.add_argument("--no-chain", action="store_true", help="skip the pivot leg")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation leg")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper-systems leg")
+    ap.add_argument("--no-hmc", action="store_true", help="skip the hybrid Monte Carlo leg")
     ap.add_argument("--paper-physics", default="",
                     help="comma-separated paper systems: only run their full MUCA + analysis")
     ap.add_argument("--physics-iters", type=int, default=1000)
@@ -509,6 +560,8 @@ def main():
         out["with_pivots"] = chain_moves_leg(wl, st)
     if not args.no_paper:
         out["paper_systems"] = paper_systems_leg(st)
+    if not args.no_hmc:
+        out["hybrid_mc"] = hmc_leg(st)
     if not args.no_diff:
         out["differentiation"] = differentiation_leg(st, args.diff_configs)
     if not args.no_cpu:
