@@ -190,13 +190,16 @@ PAPER_MAXWELL = {"cross_human": {"latent": 0.513, "barrier": 0.034},
 PAPER_SWEEPS_PER_ITERATION = {"abeta_dimer": 10 ** 6, "cross_human": 10 ** 7, "cross_rat": 10 ** 7}
 
 
-def paper_physics_leg(stream, names, iters=1000, walkers=4096, first=700, block=25):
+def paper_physics_leg(stream, names, iters=1000, walkers=4096, first=700, block=25,
+                      hmc_traj=0, hmc_steps=10, hmc_step=0.01):
     """Full multicanonical runs of the paper's example systems as in Sec. 4: `walkers` walkers
     share the paper's sweeps per iteration, `iters` Berg iterations, then the
     microcanonical analysis (Eqs. 4-8) of iterations [first, iters) in blocks of `block`:
     Maxwell construction on beta(eps), latent heat and free-energy barrier per monomer, and
     whether the caloric curve bends back (a region of negative microcanonical specific heat).
-    Flatness per iteration as the paper judges it: c_var < 5 % and peaks within 20 %."""
+    Flatness per iteration as the paper judges it: c_var < 5 % and peaks within 20 %.  With
+    hmc_traj > 0 every iteration also runs that many hybrid Monte Carlo trajectories per walker
+    (hmc_steps leapfrog steps of hmc_step) before the weight update."""
     import paper_1702_01770_amd as P
     import workloads
     out = {}
@@ -211,7 +214,12 @@ def paper_physics_leg(stream, names, iters=1000, walkers=4096, first=700, block=
         A = np.zeros((iters, sp.n_bins))
         t0 = time.perf_counter()
         for it in range(iters):
-            m.iterate(sweeps, 1)
+            if hmc_traj > 0:
+                m.sweep(sweeps)
+                m.hmc(hmc_traj, hmc_steps, hmc_step)
+                m.update_weights()
+            else:
+                m.iterate(sweeps, 1)
             B[it], A[it], _ = m.weights(0)
             if (it + 1) % 50 == 0:
                 st = m.stats_history(it, 1)[0, 0]
@@ -237,7 +245,8 @@ def paper_physics_leg(stream, names, iters=1000, walkers=4096, first=700, block=
         dbeta = np.diff(res["beta"])
         rec = {"beads": sp.n_beads, "sphere_radius": wl.box_len, "iterations": iters,
                "sweeps_per_iteration": sweeps * wl.walkers_per_system,
-               "walkers": walkers, "flat_iterations": int(flat.sum()), "flat_from": conv,
+               "walkers": walkers, "hmc_trajectories_per_iteration": hmc_traj,
+               "flat_iterations": int(flat.sum()), "flat_from": conv,
                "last_cvar_full_range": float(st[-1, 1]), "last_cvar_analysed_range": inner_cvar,
                "eps_range": [float(res["E"][0]), float(res["E"][-1])],
                "beta_c": res["beta_c"], "dbeta_c": res["dbeta_c"],
@@ -493,6 +502,8 @@ def main():
                     help="comma-separated paper systems: only run their full MUCA + analysis")
     ap.add_argument("--physics-iters", type=int, default=1000)
     ap.add_argument("--physics-walkers", type=int, default=4096)
+    ap.add_argument("--physics-hmc", type=int, default=0,
+                    help="hybrid MC trajectories per walker and iteration in the physics leg")
     ap.add_argument("--diff-only", action="store_true",
                     help="run only the differentiation leg (profiling)")
     ap.add_argument("--diff-configs", type=int, default=1_000_000)
@@ -513,7 +524,7 @@ def main():
     if args.paper_physics:
         print(json.dumps({"paper_physics": paper_physics_leg(
             st, args.paper_physics.split(","), iters=args.physics_iters,
-            walkers=args.physics_walkers,
+            walkers=args.physics_walkers, hmc_traj=args.physics_hmc,
             first=int(0.7 * args.physics_iters), block=max(1, args.physics_iters // 40))}))
         return
     if args.diff_only:
