@@ -191,7 +191,7 @@ PAPER_SWEEPS_PER_ITERATION = {"abeta_dimer": 10 ** 6, "cross_human": 10 ** 7, "c
 
 
 def paper_physics_leg(stream, names, iters=1000, walkers=4096, first=700, block=25,
-                      hmc_traj=0, hmc_steps=10, hmc_step=0.01):
+                      hmc_traj=0, hmc_steps=10, hmc_step=0.01, reset_every=0):
     """Full multicanonical runs of the paper's example systems as in Sec. 4: `walkers` walkers
     share the paper's sweeps per iteration, `iters` Berg iterations, then the
     microcanonical analysis (Eqs. 4-8) of iterations [first, iters) in blocks of `block`:
@@ -199,7 +199,10 @@ def paper_physics_leg(stream, names, iters=1000, walkers=4096, first=700, block=
     whether the caloric curve bends back (a region of negative microcanonical specific heat).
     Flatness per iteration as the paper judges it: c_var < 5 % and peaks within 20 %.  With
     hmc_traj > 0 every iteration also runs that many hybrid Monte Carlo trajectories per walker
-    (hmc_steps leapfrog steps of hmc_step) before the weight update."""
+    (hmc_steps leapfrog steps of hmc_step) before the weight update.  With reset_every > 0 the
+    recursion's accumulated statistics g are cleared every reset_every iterations before the
+    analysed range, so estimates from the early, far-from-equilibrium iterations stop weighing
+    on the weights."""
     import paper_1702_01770_amd as P
     import workloads
     out = {}
@@ -220,7 +223,9 @@ def paper_physics_leg(stream, names, iters=1000, walkers=4096, first=700, block=
                 m.update_weights()
             else:
                 m.iterate(sweeps, 1)
-            B[it], A[it], _ = m.weights(0)
+            B[it], A[it], g_now = m.weights(0)
+            if reset_every > 0 and it < first and (it + 1) % reset_every == 0:
+                m.set_weights(0, B[it], A[it], np.zeros_like(g_now))
             if (it + 1) % 50 == 0:
                 st = m.stats_history(it, 1)[0, 0]
                 print(f"[physics] {name} iteration {it + 1}/{iters} cvar {st[1]:.3f} "
@@ -246,6 +251,7 @@ def paper_physics_leg(stream, names, iters=1000, walkers=4096, first=700, block=
         rec = {"beads": sp.n_beads, "sphere_radius": wl.box_len, "iterations": iters,
                "sweeps_per_iteration": sweeps * wl.walkers_per_system,
                "walkers": walkers, "hmc_trajectories_per_iteration": hmc_traj,
+               "recursion_reset_every": reset_every,
                "flat_iterations": int(flat.sum()), "flat_from": conv,
                "last_cvar_full_range": float(st[-1, 1]), "last_cvar_analysed_range": inner_cvar,
                "eps_range": [float(res["E"][0]), float(res["E"][-1])],
@@ -502,6 +508,8 @@ def main():
                     help="comma-separated paper systems: only run their full MUCA + analysis")
     ap.add_argument("--physics-iters", type=int, default=1000)
     ap.add_argument("--physics-walkers", type=int, default=4096)
+    ap.add_argument("--physics-reset", type=int, default=0,
+                    help="clear the recursion's accumulated statistics every N iterations")
     ap.add_argument("--physics-hmc", type=int, default=0,
                     help="hybrid MC trajectories per walker and iteration in the physics leg")
     ap.add_argument("--diff-only", action="store_true",
@@ -525,6 +533,7 @@ def main():
         print(json.dumps({"paper_physics": paper_physics_leg(
             st, args.paper_physics.split(","), iters=args.physics_iters,
             walkers=args.physics_walkers, hmc_traj=args.physics_hmc,
+            reset_every=args.physics_reset,
             first=int(0.7 * args.physics_iters), block=max(1, args.physics_iters // 40))}))
         return
     if args.diff_only:
