@@ -13,7 +13,7 @@ namespace muca {
 hipError_t launch_sweep(const SweepArgs &a, bool fp64, int slots, bool periodic, int n_items,
                         int waves_per_block, size_t lds_bytes, long long n_sweeps, hipStream_t st);
 // Several walkers per wavefront (muca_sweep_pair.hip): group = lanes per walker (32 or 16),
-// slots = bead slots per lane, pos_stride = LDS coordinate stride per walker.
+// slots = bead slots per lane, pos_stride = LDS coordinate stride per walker (group * slots).
 hipError_t launch_sweep_pair(const SweepArgs &a, bool fp64, int group, int slots, bool periodic,
                              int n_items, int waves_per_block, size_t lds_bytes, long long n_sweeps,
                              int pos_stride, hipStream_t st);

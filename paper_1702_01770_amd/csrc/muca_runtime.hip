@@ -58,7 +58,6 @@ struct muca_ctx {
     int stats_cap = 4096;
     int wpb = 16, n_items = 0;
     int pack = 1;              // walkers per wave: 1 (k_sweep), 2 or 4 (k_sweep_pair)
-    int pos_stride = 0;        // LDS coordinate stride of k_sweep_pair
     bool weights_continuous = true;   // ln W continuous at every bin edge (k_sweep_pair needs it)
     bool pack_fallback = false;       // one walker per wave because of discontinuous weights
     double beta_min = 0.0, beta_max = 0.0;   // recursion bounds (off unless beta_max > beta_min)
@@ -120,9 +119,14 @@ static size_t lds_for_bins(long long bins) {
            sizeof(double) * kMaxTypes * kMaxTypes;
 }
 
+// LDS coordinate stride per walker of the several-walkers kernel: its bead slots times lanes.
+static int pair_stride(const muca_ctx *ctx, int group) {
+    return group * ((ctx->max_beads + group - 1) / group);
+}
+
 // LDS of one workgroup holding n_sys systems with `bins` bins in total.
 static size_t lds_need(const muca_ctx *ctx, long long bins, int n_sys, int wpb, int pack) {
-    return pack > 1 ? sweep_pair_lds_bytes(bins, n_sys, wpb, ctx->pos_stride, 64 / pack)
+    return pack > 1 ? sweep_pair_lds_bytes(bins, n_sys, wpb, pair_stride(ctx, 64 / pack), 64 / pack)
                     : lds_for_bins(bins);
 }
 
@@ -277,7 +281,7 @@ static int launch_chunked(muca_ctx *ctx, long long n_sweeps) {
             const int group = 64 / ctx->pack;
             CK(launch_sweep_pair(ctx->args, ctx->fp64, group, (ctx->max_beads + group - 1) / group,
                                  ctx->periodic, ctx->n_items, ctx->wpb, ctx->lds_bytes, c,
-                                 ctx->pos_stride, ctx->stream));
+                                 pair_stride(ctx, group), ctx->stream));
         }
         else
             CK(launch_sweep(ctx->args, ctx->fp64, ctx->slots, ctx->periodic, ctx->n_items, ctx->wpb,
@@ -453,7 +457,6 @@ int muca_init(const muca_config *cfg, muca_ctx **out) {
     ctx->total_bins = bin_off;
     ctx->slots = ctx->max_beads > 64 ? 2 : 1;
     ctx->npad = 64 * ctx->slots;
-    ctx->pos_stride = (ctx->max_beads + 1) & ~1;
     ctx->lds_bytes = (size_t)ctx->max_bins * (sizeof(double) * 2 + sizeof(unsigned int)) +
                      sizeof(double) * kMaxTypes * kMaxTypes;
     int dev_lds = 0;

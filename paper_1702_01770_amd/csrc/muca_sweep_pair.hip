@@ -23,7 +23,8 @@ size_t sweep_pair_lds_bytes(long long bins_total, int n_sys, int n_waves, int po
                             int group) {
     const size_t n_wl = (size_t)(64 / group) * n_waves;
     const size_t stage = (size_t)group + 1;
-    return 2 * sizeof(double2) * kMaxTypes * kMaxTypes + sizeof(Staged) * n_wl * stage +
+    return 2 * sizeof(double2) * kMaxTypes * kMaxTypes + sizeof(double) * kAngcEntries +
+           sizeof(Staged) * n_wl * stage +
            sizeof(double) * kMaxTypes * kMaxTypes + 3 * sizeof(double) * n_wl * (size_t)pos_stride +
            sizeof(double) * (size_t)(bins_total + n_sys) + sizeof(unsigned int) * (size_t)bins_total +
            sizeof(int2) * n_wl * stage + sizeof(int) * (size_t)n_sys * kMaxBeads;

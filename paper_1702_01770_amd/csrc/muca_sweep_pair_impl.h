@@ -143,6 +143,9 @@ struct Staged {
     double q0, q1, q2, lnu;
 };
 
+// Entries of the bending / torsion coefficient table (4 variants of 8).
+constexpr int kAngcEntries = 32;
+
 struct PairLds {
     const double *lw;          // ln W at the K + 1 bin edges of this walker's system
     unsigned int *hist;        // LDS histogram of this walker's system
@@ -150,16 +153,30 @@ struct PairLds {
     double *x, *y, *z;         // this walker's coordinates
     const double *ctab;        // C_LJ[t][u], t, u < kMaxTypes
     const void *kc;            // {kappa, kappa C_LJ}[intra / inter][t][u] in the accumulator type
+    const void *angc;          // bending / torsion coefficients of u_j . m, [first + 2 last][j - b + 3]
     int2 *sb;                  // staged bead index and descriptor of the next G moves (+1 spare)
     Staged *sq;                // staged random values of the next G moves (+1 spare)
 };
 
+// This lane's beads j = gl + G s from the LDS mirror (slots past the last bead hold zeros).
+template <int G, int SLOTS>
+__device__ __forceinline__ void load_lane(const PairLds &L, double (&px)[SLOTS],
+                                          double (&py)[SLOTS], double (&pz)[SLOTS]) {
+    const int gl = threadIdx.x & (G - 1);
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        const int j = gl + G * s;
+        px[s] = L.x[j]; py[s] = L.y[j]; pz[s] = L.z[j];
+    }
+}
+
 // Full FP64 energy of the walker of this group, from the LDS copy of its coordinates.
 template <int G, int SLOTS, bool PERIODIC>
 __device__ double full_energy_pair(const SweepArgs &a, int N, const PairLds &L,
-                                   const double (&px)[SLOTS], const double (&py)[SLOTS],
-                                   const double (&pz)[SLOTS], const int (&inf)[SLOTS]) {
+                                   const int (&inf)[SLOTS]) {
     const int gl = threadIdx.x & (G - 1);
+    double px[SLOTS], py[SLOTS], pz[SLOTS];
+    load_lane<G, SLOTS>(L, px, py, pz);
     double acc = 0.0;
     for (int i = 0; i < N; ++i) {
         const double xi = L.x[i], yi = L.y[i], zi = L.z[i];
@@ -225,25 +242,21 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
     const double inv_eps = a.inv_bin;
     const A2 *kct = reinterpret_cast<const A2 *>(L.kc);
 
-    // lane state: coordinates (FP64), bond to the next bead of the chain (accumulator type),
-    // descriptor, chain and row offset into the coupling table
-    double px[SLOTS], py[SLOTS], pz[SLOTS];
+    // lane state: bond to the next bead of the chain (accumulator type), descriptor, chain and
+    // row offset into the coupling table; the coordinates themselves live in the LDS mirror only
     A ux[SLOTS], uy[SLOTS], uz[SLOTS];
     int inf[SLOTS], chn[SLOTS], trow[SLOTS];
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const int j = gl + G * s;
         const bool alive = j < N;
-        px[s] = alive ? P[j] : 0.0;
-        py[s] = alive ? P[npad + j] : 0.0;
-        pz[s] = alive ? P[2 * npad + j] : 0.0;
         inf[s] = alive ? L.binfo[j] : bead_info(0, 255, true, true);
         chn[s] = bi_chain(inf[s]);
         trow[s] = bi_type(inf[s]) * kMaxTypes;
         if (alive && !bi_last(inf[s])) {
-            ux[s] = (A)(P[j + 1] - px[s]);
-            uy[s] = (A)(P[npad + j + 1] - py[s]);
-            uz[s] = (A)(P[2 * npad + j + 1] - pz[s]);
+            ux[s] = (A)(L.x[j + 1] - L.x[j]);
+            uy[s] = (A)(L.y[j + 1] - L.y[j]);
+            uz[s] = (A)(L.z[j + 1] - L.z[j]);
         } else {
             ux[s] = uy[s] = uz[s] = 0;
         }
@@ -307,12 +320,22 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             const int b = bi_nx.x, infb = bi_nx.y;
             const Staged q = L.sq[i];
             bi_nx = L.sb[i + 1];
-            A2 kk[SLOTS];
-#pragma unroll
-            for (int s = 0; s < SLOTS; ++s)
-                kk[s] = kct[(chn[s] == bi_chain(infb) ? 0 : kMaxTypes * kMaxTypes) + trow[s] + bi_type(infb)];
             const int tb = bi_type(infb), cb = bi_chain(infb);
             const bool fst = bi_first(infb), lst = bi_last(infb);
+            // coupling of every slot's bead with b, and the coefficient of u_j . m for
+            // j = b-3 .. b+2 of the same chain (0 elsewhere: entry 6)
+            const A *act = reinterpret_cast<const A *>(L.angc) + (fst ? 8 : 0) + (lst ? 16 : 0);
+            A2 kk[SLOTS];
+            A coef[SLOTS];
+            double px[SLOTS], py[SLOTS], pz[SLOTS];
+            load_lane<G, SLOTS>(L, px, py, pz);
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) {
+                const bool same = chn[s] == cb;
+                kk[s] = kct[(same ? 0 : kMaxTypes * kMaxTypes) + trow[s] + tb];
+                const unsigned ai = min((unsigned)(gl + G * s - b + 3), 6u);
+                coef[s] = act[same ? ai : 6u];
+            }
             const int bm = fst ? b : b - 1, bp = lst ? b : b + 1;
             const double xbx = L.x[b], xby = L.y[b], xbz = L.z[b];
             const double xmx = L.x[bm], xmy = L.y[bm], xmz = L.z[bm];
@@ -344,9 +367,6 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             // torsion term that uses one of them changes by a multiple of u_j . m
             const double mx = nx - xbx, my = ny - xby, mz = nz - xbz;
             const A mxa = (A)mx, mya = (A)my, mza = (A)mz;
-            const A kbend = (A)a.k_bend, ktors = (A)a.k_tors;
-            const A c_m2 = lst ? -kbend : -kbend + ktors;   // j = b-2: bend(b-2), torsion(b-2)
-            const A c_p1 = fst ? kbend : kbend - ktors;     // j = b+1: bend(b), torsion(b-1)
             A acc = 0;
 #pragma unroll
             for (int s = 0; s < SLOTS; ++s) {
@@ -382,12 +402,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 const A s3o = so * so * so, s3n = sn2 * sn2 * sn2;
                 const A t = s3n * (kk[s].x * s3n - kk[s].y) - s3o * (kk[s].x * s3o - kk[s].y);
                 acc += use ? t : (A)0;
-                A coef = (d == -2) ? c_m2 : (A)0;
-                coef = (d == 1) ? c_p1 : coef;
-                coef = (d == -3) ? -ktors : coef;
-                coef = (d == 2) ? ktors : coef;
-                coef = same ? coef : (A)0;
-                acc += coef * (ux[s] * mxa + uy[s] * mya + uz[s] * mza);
+                acc += coef[s] * (ux[s] * mxa + uy[s] * mya + uz[s] * mza);
             }
             const double dE = group_sum<G>(acc);
             const double En = E + dE;
@@ -413,7 +428,6 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                     ux[s] = lo_b ? bmx : (at_b ? bpx : ux[s]);
                     uy[s] = lo_b ? bmy : (at_b ? bpy : uy[s]);
                     uz[s] = lo_b ? bmz : (at_b ? bpz : uz[s]);
-                    if (j == b) { px[s] = nx; py[s] = ny; pz[s] = nz; }
                 }
                 L.x[b] = nx; L.y[b] = ny; L.z[b] = nz;      // every lane of the half writes
                 if (kn != k) {
@@ -437,6 +451,8 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                         const double tz = a.trans_max * (2.0 * u01(r1.w) - 1.0);
                         const double lnu_r = log(u01(r2.x));
                         const int cs = sd.chain_start[ch], ce = sd.chain_start[ch + 1];
+                        double px[SLOTS], py[SLOTS], pz[SLOTS];
+                        load_lane<G, SLOTS>(L, px, py, pz);
                         A racc = 0;
                         bool rinside = true;
                         for (int ib = cs; ib < ce; ++ib) {
@@ -474,9 +490,6 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                         n_wrej += rin ? 0u : 1u;
                         ++n_rig;
                         if (rok) {
-#pragma unroll
-                            for (int s = 0; s < SLOTS; ++s)
-                                if (chn[s] == ch) { px[s] += tx; py[s] += ty; pz[s] += tz; }
                             for (int ib = cs; ib < ce; ++ib) {     // every lane of the half writes
                                 const double xo = L.x[ib], yo = L.y[ib], zo = L.z[ib];
                                 L.x[ib] = xo + tx; L.y[ib] = yo + ty; L.z[ib] = zo + tz;
@@ -506,6 +519,8 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                     unit_from(u01(ra.y), u01(ra.z), kx, ky, kz);
                     sincos(a.pivot_max * (2.0 * u01(ra.w) - 1.0), &sn, &co);
                     const double ox = L.x[p], oy = L.y[p], oz = L.z[p];
+                    double px[SLOTS], py[SLOTS], pz[SLOTS];
+                    load_lane<G, SLOTS>(L, px, py, pz);
                     // new positions of this lane's moved beads
                     double qx[SLOTS], qy[SLOTS], qz[SLOTS];
                     A outside = 0;
@@ -595,16 +610,15 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
 #pragma unroll
                         for (int s = 0; s < SLOTS; ++s) {
                             const int j = gl + G * s;
-                            px[s] = qx[s]; py[s] = qy[s]; pz[s] = qz[s];
                             if (j >= lo && j <= hi) { L.x[j] = qx[s]; L.y[j] = qy[s]; L.z[j] = qz[s]; }
                         }
 #pragma unroll
                         for (int s = 0; s < SLOTS; ++s) {      // bonds from the new coordinates
                             const int j = gl + G * s;
                             if (j < N && !bi_last(inf[s])) {
-                                ux[s] = (A)(L.x[j + 1] - px[s]);
-                                uy[s] = (A)(L.y[j + 1] - py[s]);
-                                uz[s] = (A)(L.z[j + 1] - pz[s]);
+                                ux[s] = (A)(L.x[j + 1] - qx[s]);
+                                uy[s] = (A)(L.y[j + 1] - qy[s]);
+                                uz[s] = (A)(L.z[j + 1] - qz[s]);
                             }
                         }
                         if (pkn != k) {
@@ -629,6 +643,8 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                     for (int ib = cs; ib < ce; ++ib) { ox += L.x[ib]; oy += L.y[ib]; oz += L.z[ib]; }
                     const double inv_n = 1.0 / (double)(ce - cs);
                     ox *= inv_n; oy *= inv_n; oz *= inv_n;
+                    double px[SLOTS], py[SLOTS], pz[SLOTS];
+                    load_lane<G, SLOTS>(L, px, py, pz);
                     A racc = 0;
                     bool rinside = true;
                     for (int ib = cs; ib < ce; ++ib) {
@@ -699,7 +715,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 }   // CHAIN
                 ++S;
                 if (a.resync_sweeps > 0 && (S % (unsigned long long)a.resync_sweeps) == 0) {
-                    const double Ef = full_energy_pair<G, SLOTS, PERIODIC>(a, N, L, px, py, pz, inf);
+                    const double Ef = full_energy_pair<G, SLOTS, PERIODIC>(a, N, L, inf);
                     const double dr = fabs(Ef - E);
                     max_drift = fmax(max_drift, dr);
                     if (dr > a.drift_tol && gl == 0) set_error(a.err, -5);
@@ -725,7 +741,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const int j = gl + G * s;
-        if (j < N) { P[j] = px[s]; P[npad + j] = py[s]; P[2 * npad + j] = pz[s]; }
+        if (j < N) { P[j] = L.x[j]; P[npad + j] = L.y[j]; P[2 * npad + j] = L.z[j]; }
     }
     if (gl == 0) {
         a.energy[w] = E;
@@ -747,14 +763,17 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
 
 
 // LDS layout (per workgroup), 16-byte items first: the {kappa, kappa C_LJ} table (intra, inter)
-// in the accumulator type; the staged draws of every walker; the C_LJ table; the x, y and z
-// coordinate mirrors of every walker (stride pos_stride); ln W at the bin edges of every system
-// of the workgroup (system i at lds_off[i] + i); the staged bead indices and descriptors of every
-// walker; the 32-bit histograms (system i at lds_off[i]); the bead descriptors of every system.
+// in the accumulator type; the bending / torsion coefficient table; the staged draws of every
+// walker; the C_LJ table; the coordinate mirror of every walker (x, y, z blocks of pos_stride =
+// G * SLOTS doubles each, so one address with constant offsets reaches all three, zeros past the
+// last bead); ln W at the bin edges of every system of the workgroup (system i at
+// lds_off[i] + i); the staged bead indices and descriptors of every walker; the 32-bit
+// histograms (system i at lds_off[i]); the bead descriptors of every system.
 template <bool FP64, int G, int SLOTS, bool PERIODIC, bool CHAIN>
-__global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_sweeps, int pos_stride) {
+__global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_sweeps) {
     constexpr int kStage = G + 1;   // staged moves per walker (+1 spare for the prefetch)
     constexpr int kPer = 64 / G;    // walkers per wave
+    constexpr int kStride = G * SLOTS;
     using A = AccP<FP64>;
     using A2 = typename std::conditional<FP64, double2, float2>::type;
     extern __shared__ double2 lds_p[];
@@ -764,12 +783,11 @@ __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_swe
     const int n_wl = kPer * n_waves;
     const int bins_total = wi.lds_off[ns - 1] + a.sys[wi.sys[ns - 1]].n_bins;
     A2 *kc = reinterpret_cast<A2 *>(lds_p);
-    Staged *sq = reinterpret_cast<Staged *>(lds_p + 2 * kMaxTypes * kMaxTypes);
+    A *angc = reinterpret_cast<A *>(lds_p + 2 * kMaxTypes * kMaxTypes);
+    Staged *sq = reinterpret_cast<Staged *>(lds_p + 2 * kMaxTypes * kMaxTypes + kAngcEntries / 2);
     double *ctab = reinterpret_cast<double *>(sq + (size_t)n_wl * kStage);
-    double *px = ctab + kMaxTypes * kMaxTypes;
-    double *py = px + (size_t)n_wl * pos_stride;
-    double *pz = py + (size_t)n_wl * pos_stride;
-    double *lw = pz + (size_t)n_wl * pos_stride;
+    double *pc = ctab + kMaxTypes * kMaxTypes;
+    double *lw = pc + (size_t)n_wl * 3 * kStride;
     int2 *sb = reinterpret_cast<int2 *>(lw + bins_total + ns);
     unsigned int *hist = reinterpret_cast<unsigned int *>(sb + n_wl * kStage);
     int *binfo = reinterpret_cast<int *>(hist + bins_total);
@@ -798,17 +816,34 @@ __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_swe
         v.y = (A)(kap * c);
         kc[threadIdx.x] = v;
     }
+    if (threadIdx.x < kAngcEntries) {
+        // A move of bead b by m changes bond b-1 by +m and bond b by -m, so the bending and
+        // torsion terms that pair one of them with another bond u_j change by a multiple of
+        // u_j . m: j = b-3 torsion(b-3); j = b-2 bend(b-2) and, unless b ends its chain,
+        // torsion(b-2); j = b+1 bend(b) and, unless b starts its chain, torsion(b-1);
+        // j = b+2 torsion(b).  Entries 2, 3, 6, 7 are zero (6 serves every other lane).
+        const int i = threadIdx.x & 7;
+        const bool first = (threadIdx.x >> 3) & 1, last = (threadIdx.x >> 4) & 1;
+        const A kb = (A)a.k_bend, kt = (A)a.k_tors;
+        A c = (A)0;
+        if (i == 0) c = -kt;
+        if (i == 1) c = last ? -kb : -kb + kt;
+        if (i == 4) c = first ? kb : kb - kt;
+        if (i == 5) c = kt;
+        angc[threadIdx.x] = c;
+    }
     const int wave = threadIdx.x >> 6;
     const int grp = (threadIdx.x & 63) / G;
     const int w0 = wi.walker[wave];
     const int wl = kPer * wave + grp;
-    if (w0 >= 0) {                  // coordinate mirror of this half's walker
+    double *mine = pc + (size_t)wl * 3 * kStride;
+    if (w0 >= 0) {                  // coordinate mirror of this group's walker
         const int N = a.sys[wi.sys[wi.slot[wave]]].n_beads;
         const double *P = a.pos + (size_t)(w0 + grp) * 3 * a.npad;
-        for (int j = threadIdx.x & (G - 1); j < N; j += G) {
-            px[(size_t)wl * pos_stride + j] = P[j];
-            py[(size_t)wl * pos_stride + j] = P[a.npad + j];
-            pz[(size_t)wl * pos_stride + j] = P[2 * a.npad + j];
+        for (int j = threadIdx.x & (G - 1); j < kStride; j += G) {
+            mine[j] = j < N ? P[j] : 0.0;
+            mine[kStride + j] = j < N ? P[a.npad + j] : 0.0;
+            mine[2 * kStride + j] = j < N ? P[2 * a.npad + j] : 0.0;
         }
     }
     __syncthreads();
@@ -820,11 +855,12 @@ __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_swe
         L.lw = lw + wi.lds_off[i] + i;
         L.hist = hist + wi.lds_off[i];
         L.binfo = binfo + i * kMaxBeads;
-        L.x = px + (size_t)wl * pos_stride;
-        L.y = py + (size_t)wl * pos_stride;
-        L.z = pz + (size_t)wl * pos_stride;
+        L.x = mine;
+        L.y = mine + kStride;
+        L.z = mine + 2 * kStride;
         L.ctab = ctab;
         L.kc = kc;
+        L.angc = angc;
         L.sb = sb + wl * kStage;
         L.sq = sq + (size_t)wl * kStage;
         run_pair<FP64, G, SLOTS, PERIODIC, CHAIN>(a, sd, w0 + grp, L, n_sweeps);
@@ -843,12 +879,13 @@ __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_swe
 template <bool FP64, int G, int SLOTS, bool PERIODIC, bool CHAIN>
 static hipError_t launch_pair_t(const SweepArgs &a, int n_items, int waves, size_t lds,
                                 long long n_sweeps, int pos_stride, hipStream_t st) {
-    if (waves < 1 || waves > 8 || pos_stride < 1) return hipErrorInvalidValue;   // __launch_bounds__(512)
+    // __launch_bounds__(512); the LDS size was computed for this coordinate stride
+    if (waves < 1 || waves > 8 || pos_stride != G * SLOTS) return hipErrorInvalidValue;
     auto kern = k_sweep_pair<FP64, G, SLOTS, PERIODIC, CHAIN>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(n_items), dim3(64 * waves), lds, st, a, n_sweeps, pos_stride);
+    hipLaunchKernelGGL(kern, dim3(n_items), dim3(64 * waves), lds, st, a, n_sweeps);
     return hipGetLastError();
 }
 
