@@ -70,7 +70,10 @@ enum { MUCA_PREC_FP64 = 0, MUCA_PREC_FP32_SPLIT = 1 };
  * waves_per_block: wavefronts per workgroup (0 = library default).  walkers_per_wave: 1 runs
  * one walker per 64-lane wavefront; 2 or 4 run that many walkers of a system in 32- or 16-lane
  * groups of a wavefront (walkers_per_system a multiple of it, at most 8 waves per block; 4 also
- * needs at most 64 beads per system); 0 lets the library choose (2 when possible).  Several
+ * needs at most 64 beads per system); MUCA_WALKERS_MIXED (-1) picks per system by chain length
+ * (the longest chains one walker per wave, the shortest four, the rest two; walkers_per_system
+ * a multiple of 4, at most 64 beads, 8 waves per block; init fails when no chain is long enough
+ * to gain from it); 0 lets the library choose (2 when possible).  Several
  * walkers per wave read ln W from its values at the bin edges, which needs continuous weights
  * (the two lines of Eq. 8 meeting at every inner bin edge agree there, as the weight recursion
  * maintains); weights set through muca_set_weights or muca_set_state that are not switch the
@@ -110,14 +113,19 @@ typedef struct {
     void *stream;
 } muca_config;
 
+/* walkers_per_wave of the mixed plan (1, 2 or 4 walkers per wave chosen per system). */
+#define MUCA_WALKERS_MIXED (-1)
+
 /* Launch plan of the sweep (muca_get_launch_info). */
 typedef struct {
-    int32_t walkers_per_wave;   /* 1, 2 or 4 */
+    int32_t walkers_per_wave;   /* 1, 2, 4 or MUCA_WALKERS_MIXED */
     int32_t waves_per_block;
     int32_t paired;             /* 1: workgroups mix a long and a short system */
     int32_t workgroups;         /* workgroups per sweep launch */
     int64_t lds_bytes;          /* dynamic LDS per workgroup */
     int64_t sweeps_per_launch;  /* muca_sweep(n) issues ceil(n / sweeps_per_launch) launches */
+    int32_t lanes_used;         /* bit 0, 1, 2 set when some wave runs walkers on 16, 32, 64
+                                   lanes (one walker per wave: 64) */
 } muca_launch_info;
 
 /* Per-system statistics of one weight update (flatness as in Sec. 4.1). */
@@ -219,7 +227,8 @@ int muca_set_state(muca_ctx *ctx, const void *buf, size_t bytes);
 
 /* Time the candidate sweep launches (one, two or four walkers per wave; 16, 8, 4, 2 or 1
  * waves per workgroup; with several systems, with and without pairing long and short chains in
- * one workgroup) on probe_sweeps sweeps, keep the fastest and restore the sampling state, so
+ * one workgroup; last the mixed plan, kept only when more than 3 % faster than the best of the
+ * others) on probe_sweeps sweeps, keep the fastest and restore the sampling state, so
  * results do not depend on tuning (every walker's trajectory is independent of the schedule).
  * Candidates whose LDS does not fit are skipped.  *chosen (host, may be NULL) receives the waves
  * per workgroup, negated for an unpaired schedule; muca_get_launch_info gives the full plan. */

@@ -48,7 +48,7 @@ class WalkerCounters(C.Structure):
 class LaunchInfo(C.Structure):
     _fields_ = [("walkers_per_wave", C.c_int32), ("waves_per_block", C.c_int32),
                 ("paired", C.c_int32), ("workgroups", C.c_int32), ("lds_bytes", C.c_int64),
-                ("sweeps_per_launch", C.c_int64)]
+                ("sweeps_per_launch", C.c_int64), ("lanes_used", C.c_int32)]
 
 
 class AnalysisIn(C.Structure):

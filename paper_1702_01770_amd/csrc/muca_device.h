@@ -40,6 +40,7 @@ struct WorkItem {
     int lds_off[kMaxWgSys];
     int walker[kMaxWgWaves];   // walker id of each wave, -1 = idle wave
     int slot[kMaxWgWaves];     // index into sys[] of each wave
+    int kind[kMaxWgWaves];     // lanes per walker of each wave (mixed plan of k_sweep_pair)
 };
 
 // Counter slots per walker in WalkerDev::cnt.

@@ -13,17 +13,21 @@ namespace muca {
 hipError_t launch_sweep(const SweepArgs &a, bool fp64, int slots, bool periodic, int n_items,
                         int waves_per_block, size_t lds_bytes, long long n_sweeps, hipStream_t st);
 // Several walkers per wavefront (muca_sweep_pair.hip): group = lanes per walker (32 or 16),
-// slots = bead slots per lane, pos_stride = LDS coordinate stride per walker (group * slots).
+// slots = bead slots per lane; group = 0 runs the mixed plan (lanes per walker per wave from
+// WorkItem::kind: 16 with 2 slots, 32 with 2 slots, 64 with 1 slot).
 hipError_t launch_sweep_pair(const SweepArgs &a, bool fp64, int group, int slots, bool periodic,
                              int n_items, int waves_per_block, size_t lds_bytes, long long n_sweeps,
-                             int pos_stride, hipStream_t st);
-size_t sweep_pair_lds_bytes(long long bins_total, int n_sys, int n_waves, int pos_stride,
-                            int group);
+                             hipStream_t st);
+size_t sweep_pair_lds_bytes(long long bins_total, int n_sys, int n_waves, int group, int slots);
+// Per-wave LDS slabs of the several-walkers kernel: staged moves (64 / group walkers with
+// group + 1 entries each) and coordinate mirrors (three blocks of group * slots doubles per
+// walker); the mixed plan takes the largest of its three kinds.
+constexpr int pair_slab_stage(int group) { return group ? (64 / group) * (group + 1) : 68; }
+constexpr int pair_slab_coord(int group, int slots) { return group ? 3 * 64 * slots : 384; }
 // The same with pivots / chain rotations compiled in (muca_sweep_pair_chain.hip).
 hipError_t launch_sweep_pair_chain(const SweepArgs &a, bool fp64, int group, int slots,
                                    bool periodic, int n_items, int waves_per_block,
-                                   size_t lds_bytes, long long n_sweeps, int pos_stride,
-                                   hipStream_t st);
+                                   size_t lds_bytes, long long n_sweeps, hipStream_t st);
 // Hybrid Monte Carlo trajectories (muca_hmc.hip): one wave per walker, at most 64 beads.
 struct HmcArgs {
     const int *walker_sys;          // system of every walker

@@ -34,6 +34,8 @@ struct SysHost {
 
 }  // namespace
 
+constexpr int kPackMixed = MUCA_WALKERS_MIXED;   // muca_ctx::pack of the mixed plan
+
 struct muca_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -57,7 +59,10 @@ struct muca_ctx {
     IterStatsDev *d_stats = nullptr;
     int stats_cap = 4096;
     int wpb = 16, n_items = 0;
-    int pack = 1;              // walkers per wave: 1 (k_sweep), 2 or 4 (k_sweep_pair)
+    int pack = 1;              // walkers per wave: 1 (k_sweep), 2 or 4 (k_sweep_pair), or
+                               // kPackMixed (k_sweep_pair, lanes per walker per system in kind)
+    std::vector<int> kind;     // mixed plan: lanes per walker (16, 32 or 64) of every system
+    int n_cu = 0;              // compute units of the device
     bool weights_continuous = true;   // ln W continuous at every bin edge (k_sweep_pair needs it)
     bool pack_fallback = false;       // one walker per wave because of discontinuous weights
     double beta_min = 0.0, beta_max = 0.0;   // recursion bounds (off unless beta_max > beta_min)
@@ -119,14 +124,17 @@ static size_t lds_for_bins(long long bins) {
            sizeof(double) * kMaxTypes * kMaxTypes;
 }
 
-// LDS coordinate stride per walker of the several-walkers kernel: its bead slots times lanes.
-static int pair_stride(const muca_ctx *ctx, int group) {
-    return group * ((ctx->max_beads + group - 1) / group);
+// Lanes per walker and bead slots per lane of the several-walkers kernel for a plan (0, 0: the
+// mixed plan, whose kinds fix their slots).
+static int pair_group(int pack) { return pack > 0 ? 64 / pack : 0; }
+static int pair_slots(const muca_ctx *ctx, int pack) {
+    const int g = pair_group(pack);
+    return g ? (ctx->max_beads + g - 1) / g : 0;
 }
 
 // LDS of one workgroup holding n_sys systems with `bins` bins in total.
 static size_t lds_need(const muca_ctx *ctx, long long bins, int n_sys, int wpb, int pack) {
-    return pack > 1 ? sweep_pair_lds_bytes(bins, n_sys, wpb, pair_stride(ctx, 64 / pack), 64 / pack)
+    return pack != 1 ? sweep_pair_lds_bytes(bins, n_sys, wpb, pair_group(pack), pair_slots(ctx, pack))
                     : lds_for_bins(bins);
 }
 
@@ -139,8 +147,66 @@ static bool has_chain_moves(const muca_ctx *ctx) {
 // 64 beads (four slots of 16 lanes), 2 an even number of walkers; both need continuous weights.
 static bool pack_ok(const muca_ctx *ctx, int pack) {
     if (pack == 1) return !has_chain_moves(ctx);
+    if (pack == kPackMixed)
+        return ctx->weights_continuous && ctx->W % 4 == 0 && ctx->max_beads <= 64;
     if (!ctx->weights_continuous || ctx->W % pack != 0) return false;
     return pack == 2 || (pack == 4 && ctx->max_beads <= 64);
+}
+
+static int build_schedule(muca_ctx *ctx, int wpb, bool pair, int pack);
+
+// Mixed plan.  A sweep of a chain of N beads takes about N move times on 16- or 32-lane groups
+// (two bead slots) and about 0.8 N on a whole wave (one slot, no second slot's pair terms), and a
+// launch lasts as long as its slowest walker.  So the longest chains go to one walker per wave,
+// longest first, while that still shortens the slowest sweep (N >= 0.8 N_max); every such system
+// needs W / 2 more waves, made up by moving the shortest chains (N <= 32) to four walkers per
+// wave, so that all waves stay resident (8 per CU); chains of at most 16 beads always run four
+// per wave.  Fails when no system would move.
+static int plan_mixed(muca_ctx *ctx) {
+    const int n = ctx->n_sys, W = ctx->W;
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return ctx->sys[a].n_beads > ctx->sys[b].n_beads;
+    });
+    const int budget = 8 * std::max(1, ctx->n_cu);
+    const int nmax = ctx->sys[order[0]].n_beads;
+    for (int n64 = n; n64 >= 1; --n64) {
+        // chains of at most 16 beads fill one slot of 16 lanes: four walkers per wave cost them
+        // nothing
+        std::vector<int> kind(n, 32);
+        long long total = (long long)n * W / 2;
+        int lo_short = n - 1, moved = 0;
+        while (lo_short >= 0 && ctx->sys[order[lo_short]].n_beads <= 16) {
+            kind[order[lo_short]] = 16;
+            total -= W / 4;
+            --lo_short;
+        }
+        for (int r = 0; r < n && moved < n64; ++r) {
+            const int s = order[r];
+            const int N = ctx->sys[s].n_beads;
+            if (N <= 32 || 5 * N < 4 * nmax) break;
+            while (total + W / 2 > budget && lo_short > r &&
+                   ctx->sys[order[lo_short]].n_beads <= 32) {
+                kind[order[lo_short]] = 16;
+                total -= W / 4;
+                --lo_short;
+            }
+            if (total + W / 2 > budget) break;
+            kind[s] = 64;
+            total += W / 2;
+            ++moved;
+        }
+        if (moved == 0) break;
+        ctx->kind = kind;
+        const int rc = build_schedule(ctx, 8, true, kPackMixed);
+        if (rc == MUCA_OK && ctx->n_items <= std::max(1, ctx->n_cu)) return MUCA_OK;
+        if (rc != MUCA_OK && rc != MUCA_E_INVAL) return rc;
+        ctx->err.clear();
+        if (moved < n64) n64 = moved;       // retry with one system fewer on whole waves
+    }
+    return fail(ctx, MUCA_E_INVAL, "no mixed plan: no chain is long enough to gain from one "
+                                   "walker per wave, or its waves do not fit");
 }
 
 // Workgroup schedule.  A workgroup runs wpb waves of `pack` walkers each (consecutive walkers of
@@ -151,6 +217,12 @@ static bool pack_ok(const muca_ctx *ctx, int pack) {
 // longest chains are listed first.
 static int build_schedule(muca_ctx *ctx, int wpb, bool pair, int pack) {
     const int dev_lds = (int)ctx->lds_limit;
+    // walkers per wave of every system
+    std::vector<int> wpw(ctx->n_sys, pack);
+    if (pack == kPackMixed) {
+        if ((int)ctx->kind.size() != ctx->n_sys) return fail(ctx, MUCA_E_INVAL, "no mixed plan");
+        for (int s = 0; s < ctx->n_sys; ++s) wpw[s] = 64 / ctx->kind[s];
+    }
     std::vector<WorkItem> items;
     std::vector<int> order(ctx->n_sys);
     for (int s = 0; s < ctx->n_sys; ++s) order[s] = s;
@@ -161,7 +233,7 @@ static int build_schedule(muca_ctx *ctx, int wpb, bool pair, int pack) {
     auto blank = []() {
         WorkItem w{};
         w.n_sys = 0;
-        for (int i = 0; i < kMaxWgWaves; ++i) { w.walker[i] = -1; w.slot[i] = 0; }
+        for (int i = 0; i < kMaxWgWaves; ++i) { w.walker[i] = -1; w.slot[i] = 0; w.kind[i] = 0; }
         return w;
     };
     size_t lds_max = 0;
@@ -178,7 +250,8 @@ static int build_schedule(muca_ctx *ctx, int wpb, bool pair, int pack) {
                 w.n_sys = 1; w.sys[0] = A; w.lds_off[0] = 0;
                 for (int v = 0; v < wpb && next[A] < ctx->W; ++v) {
                     w.walker[v] = ctx->sys[A].walker_off + next[A];
-                    next[A] += pack;
+                    w.kind[v] = 64 / wpw[A];
+                    next[A] += wpw[A];
                 }
                 items.push_back(w);
             }
@@ -198,10 +271,12 @@ static int build_schedule(muca_ctx *ctx, int wpb, bool pair, int pack) {
                 const bool use_a = ((v / 4) % 2) == 0;
                 if (use_a && na < half && next[A] < ctx->W) {
                     w.walker[v] = ctx->sys[A].walker_off + next[A]; w.slot[v] = 0; ++na;
-                    next[A] += pack;
+                    w.kind[v] = 64 / wpw[A];
+                    next[A] += wpw[A];
                 } else if (!use_a && nb < half && next[B] < ctx->W) {
                     w.walker[v] = ctx->sys[B].walker_off + next[B]; w.slot[v] = 1; ++nb;
-                    next[B] += pack;
+                    w.kind[v] = 64 / wpw[B];
+                    next[B] += wpw[B];
                 }
             }
             items.push_back(w);
@@ -250,7 +325,7 @@ static int refresh_continuity(muca_ctx *ctx) {
     if (!ok && has_chain_moves(ctx))
         return fail(ctx, MUCA_E_INVAL, "chain moves need continuous weights (ln W equal on both "
                                        "sides of every bin edge)");
-    if (!ok && ctx->pack > 1) {
+    if (!ok && ctx->pack != 1) {
         const int rc = build_schedule(ctx, std::min(16, ctx->W), true, 1);
         if (rc != MUCA_OK) return rc;
         ctx->pack_fallback = true;
@@ -277,11 +352,10 @@ static int launch_chunked(muca_ctx *ctx, long long n_sweeps) {
     long long left = n_sweeps;
     while (left > 0) {
         const long long c = std::min<long long>(left, ctx->chunk_sweeps);
-        if (ctx->pack > 1) {
-            const int group = 64 / ctx->pack;
-            CK(launch_sweep_pair(ctx->args, ctx->fp64, group, (ctx->max_beads + group - 1) / group,
-                                 ctx->periodic, ctx->n_items, ctx->wpb, ctx->lds_bytes, c,
-                                 pair_stride(ctx, group), ctx->stream));
+        if (ctx->pack != 1) {
+            CK(launch_sweep_pair(ctx->args, ctx->fp64, pair_group(ctx->pack),
+                                 pair_slots(ctx, ctx->pack), ctx->periodic, ctx->n_items, ctx->wpb,
+                                 ctx->lds_bytes, c, ctx->stream));
         }
         else
             CK(launch_sweep(ctx->args, ctx->fp64, ctx->slots, ctx->periodic, ctx->n_items, ctx->wpb,
@@ -378,9 +452,10 @@ static int validate(const muca_config *c, std::string &why) {
         (c->walkers_per_wave == 1 || c->walkers_per_system % 2 != 0)) { why = "chain moves need two or four walkers per wave (an even walkers_per_system)"; return MUCA_E_INVAL; }
     if (c->waves_per_block < 0 || c->waves_per_block > 16) { why = "waves_per_block must be 0..16"; return MUCA_E_INVAL; }
     if (c->walkers_per_wave != 0 && c->walkers_per_wave != 1 && c->walkers_per_wave != 2 &&
-        c->walkers_per_wave != 4) { why = "walkers_per_wave must be 0, 1, 2 or 4"; return MUCA_E_INVAL; }
+        c->walkers_per_wave != 4 && c->walkers_per_wave != kPackMixed) { why = "walkers_per_wave must be 0, 1, 2, 4 or -1 (mixed)"; return MUCA_E_INVAL; }
+    if (c->walkers_per_wave == kPackMixed && c->walkers_per_system % 4 != 0) { why = "the mixed plan needs a multiple of 4 walkers_per_system"; return MUCA_E_INVAL; }
     if (c->walkers_per_wave > 1 && (c->walkers_per_system % c->walkers_per_wave) != 0) { why = "walkers_per_system must be a multiple of walkers_per_wave"; return MUCA_E_INVAL; }
-    if (c->walkers_per_wave > 1 && c->waves_per_block > 8) { why = "more than one walker per wave allows at most 8 waves per block"; return MUCA_E_INVAL; }
+    if ((c->walkers_per_wave > 1 || c->walkers_per_wave == kPackMixed) && c->waves_per_block > 8) { why = "more than one walker per wave allows at most 8 waves per block"; return MUCA_E_INVAL; }
     if (!std::isfinite(c->beta_min) || !std::isfinite(c->beta_max)) { why = "beta bounds must be finite"; return MUCA_E_INVAL; }
     return MUCA_OK;
 }
@@ -619,6 +694,21 @@ int muca_init(const muca_config *cfg, muca_ctx **out) {
     ctx->chunk_sweeps = std::max(1, 200000 / std::max(1, ctx->max_beads));
     ctx->lds_limit = (size_t)dev_lds;
     // default: two walkers per wave when the walkers pair up, 8 such waves per workgroup
+    if (hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device) !=
+        hipSuccess) {
+        ctx->err = "no HIP device";
+        return bail(MUCA_E_DEVICE);
+    }
+    if (cfg->walkers_per_wave == kPackMixed) {
+        if (ctx->max_beads > 64) {
+            ctx->err = "the mixed plan needs at most 64 beads per system";
+            return bail(MUCA_E_INVAL);
+        }
+        rc = plan_mixed(ctx);
+        if (rc != MUCA_OK) return bail(rc);
+        *out = ctx;
+        return MUCA_OK;
+    }
     int pack = cfg->walkers_per_wave > 0 ? cfg->walkers_per_wave : (ctx->W % 2 == 0 ? 2 : 1);
     if (cfg->walkers_per_wave == 4 && ctx->max_beads > 64) {
         ctx->err = "four walkers per wave need at most 64 beads per system";
@@ -1025,6 +1115,12 @@ int muca_get_launch_info(muca_ctx *ctx, muca_launch_info *out) {
     out->workgroups = ctx->n_items;
     out->lds_bytes = (int64_t)ctx->lds_bytes;
     out->sweeps_per_launch = ctx->chunk_sweeps;
+    out->lanes_used = 0;
+    if (ctx->pack == kPackMixed) {
+        for (int k : ctx->kind) out->lanes_used |= k == 16 ? 1 : (k == 32 ? 2 : 4);
+    } else {
+        out->lanes_used = ctx->pack == 4 ? 1 : (ctx->pack == 2 ? 2 : 4);
+    }
     return MUCA_OK;
 }
 
@@ -1049,13 +1145,14 @@ int muca_autotune(muca_ctx *ctx, int64_t probe_sweeps, int32_t *chosen) {
                 cands.push_back(Cand{pack, c, pr != 0});
             }
     }
+    if (pack_ok(ctx, kPackMixed)) cands.push_back(Cand{kPackMixed, 8, true});
     Cand best{ctx->pack, ctx->wpb, ctx->paired};
     float best_ms = 1e30f;
     hipEvent_t e0, e1;
     CK(hipEventCreate(&e0));
     CK(hipEventCreate(&e1));
     for (const Cand &cd : cands) {
-        rc = build_schedule(ctx, cd.wpb, cd.pair, cd.pack);
+        rc = cd.pack == kPackMixed ? plan_mixed(ctx) : build_schedule(ctx, cd.wpb, cd.pair, cd.pack);
         if (rc == MUCA_E_INVAL) { rc = MUCA_OK; continue; }   // does not fit in LDS
         if (rc != MUCA_OK) break;
         rc = launch_chunked(ctx, 1);                 // warm the code path
@@ -1067,7 +1164,10 @@ int muca_autotune(muca_ctx *ctx, int64_t probe_sweeps, int32_t *chosen) {
         CK(hipEventSynchronize(e1));
         float ms = 0.f;
         CK(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best_ms) { best_ms = ms; best = cd; }
+        // the mixed plan is tried last and kept only when clearly faster (3 %), so that near
+        // ties keep the uniform plan
+        const float need = cd.pack == kPackMixed ? 0.97f * best_ms : best_ms;
+        if (ms < need) { best_ms = ms; best = cd; }
         rc = muca_set_state(ctx, saved.data(), bytes);
         if (rc != MUCA_OK) break;
     }
@@ -1076,7 +1176,7 @@ int muca_autotune(muca_ctx *ctx, int64_t probe_sweeps, int32_t *chosen) {
     if (rc != MUCA_OK) return rc;
     rc = sync_and_check(ctx);
     if (rc != MUCA_OK) return rc;
-    rc = build_schedule(ctx, best.wpb, best.pair, best.pack);
+    rc = best.pack == kPackMixed ? plan_mixed(ctx) : build_schedule(ctx, best.wpb, best.pair, best.pack);
     if (rc != MUCA_OK) return rc;
     ctx->err.clear();
     if (chosen) *chosen = best.pair ? best.wpb : -best.wpb;

@@ -19,25 +19,23 @@
 
 namespace muca {
 
-size_t sweep_pair_lds_bytes(long long bins_total, int n_sys, int n_waves, int pos_stride,
-                            int group) {
-    const size_t n_wl = (size_t)(64 / group) * n_waves;
-    const size_t stage = (size_t)group + 1;
+size_t sweep_pair_lds_bytes(long long bins_total, int n_sys, int n_waves, int group, int slots) {
+    const size_t stage = (size_t)n_waves * pair_slab_stage(group);
+    const size_t coord = (size_t)n_waves * pair_slab_coord(group, slots);
     return 2 * sizeof(double2) * kMaxTypes * kMaxTypes + sizeof(double) * kAngcEntries +
-           sizeof(Staged) * n_wl * stage +
-           sizeof(double) * kMaxTypes * kMaxTypes + 3 * sizeof(double) * n_wl * (size_t)pos_stride +
+           sizeof(Staged) * stage + sizeof(double) * kMaxTypes * kMaxTypes + sizeof(double) * coord +
            sizeof(double) * (size_t)(bins_total + n_sys) + sizeof(unsigned int) * (size_t)bins_total +
-           sizeof(int2) * n_wl * stage + sizeof(int) * (size_t)n_sys * kMaxBeads;
+           sizeof(int2) * stage + sizeof(int) * (size_t)n_sys * kMaxBeads;
 }
 
 hipError_t launch_sweep_pair(const SweepArgs &a, bool fp64, int group, int slots, bool periodic,
-                             int n_items, int waves, size_t lds, long long n_sweeps, int pos_stride,
+                             int n_items, int waves, size_t lds, long long n_sweeps,
                              hipStream_t st) {
     if (a.pivot_per_sweep > 0 || a.rotate_per_sweep > 0)
         return launch_sweep_pair_chain(a, fp64, group, slots, periodic, n_items, waves, lds,
-                                       n_sweeps, pos_stride, st);
+                                       n_sweeps, st);
     return launch_pair_all<false>(a, fp64, group, slots, periodic, n_items, waves, lds, n_sweeps,
-                                  pos_stride, st);
+                                  st);
 }
 
 }  // namespace muca

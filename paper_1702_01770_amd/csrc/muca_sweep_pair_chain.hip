@@ -6,9 +6,9 @@ namespace muca {
 
 hipError_t launch_sweep_pair_chain(const SweepArgs &a, bool fp64, int group, int slots,
                                    bool periodic, int n_items, int waves, size_t lds,
-                                   long long n_sweeps, int pos_stride, hipStream_t st) {
+                                   long long n_sweeps, hipStream_t st) {
     return launch_pair_all<true>(a, fp64, group, slots, periodic, n_items, waves, lds, n_sweeps,
-                                 pos_stride, st);
+                                 st);
 }
 
 }  // namespace muca

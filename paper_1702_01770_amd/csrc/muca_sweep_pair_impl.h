@@ -82,11 +82,24 @@ __device__ __forceinline__ double half_sum_f(float v) {
     v += dpp_f<0x140>(v);
     return row_pair_sum((double)v);
 }
+// Sum of the two 32-lane halves of the wave, returned to every lane (gfx950's half swap, with
+// the 64-bit pattern of row_pair_sum).
+__device__ __forceinline__ double halves_sum(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
+    const auto sl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto sh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    const double a = __builtin_bit_cast(double, ((unsigned long long)sh[0] << 32) | sl[0]);
+    const double b = __builtin_bit_cast(double, ((unsigned long long)sh[1] << 32) | sl[1]);
+    return a + b;
+}
 // Sum over the G lanes of each group, returned to every lane of the group: for G = 16 the DPP
-// row butterfly alone, for G = 32 followed by the row swap.
+// row butterfly alone, for G = 32 followed by the row swap, for G = 64 then the half swap.
 template <int G>
 __device__ __forceinline__ double group_sum(double v) {
-    if constexpr (G == 32) {
+    if constexpr (G == 64) {
+        return halves_sum(half_sum_d(v));
+    } else if constexpr (G == 32) {
         return half_sum_d(v);
     } else {
         v += dpp_d<0xB1>(v);
@@ -98,7 +111,9 @@ __device__ __forceinline__ double group_sum(double v) {
 }
 template <int G>
 __device__ __forceinline__ double group_sum(float v) {
-    if constexpr (G == 32) {
+    if constexpr (G == 64) {
+        return halves_sum(half_sum_f(v));
+    } else if constexpr (G == 32) {
         return half_sum_f(v);
     } else {
         v += dpp_f<0xB1>(v);
@@ -389,10 +404,9 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 }
                 const A fxo = (A)dxo, fyo = (A)dyo, fzo = (A)dzo;
                 const A fxn = (A)dxn, fyn = (A)dyn, fzn = (A)dzn;
-                A r2o = fxo * fxo + fyo * fyo + fzo * fzo;
-                A r2n = fxn * fxn + fyn * fyn + fzn * fzn;
-                r2o = use ? r2o : (A)1;
-                r2n = use ? r2n : (A)1;
+                // unused lanes (r2 may be 0 there) are dropped by the select below
+                const A r2o = fxo * fxo + fyo * fyo + fzo * fzo;
+                const A r2n = fxn * fxn + fyn * fyn + fzn * fzn;
                 A so, sn2;
                 if constexpr (FP64) {
                     so = 1.0 / r2o; sn2 = 1.0 / r2n;
@@ -762,34 +776,91 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
 }  // namespace
 
 
+// Mirror of the coordinates of this wave's walkers: x, y, z blocks of G * SLOTS doubles per
+// walker (one address with constant offsets reaches all three), zeros past the last bead.
+template <int G, int SLOTS>
+__device__ void pair_mirror(const SweepArgs &a, const WorkItem &wi, int wave, double *slab) {
+    constexpr int kStride = G * SLOTS;
+    const int w0 = wi.walker[wave];
+    if (w0 < 0) return;
+    const int grp = (threadIdx.x & 63) / G;
+    double *mine = slab + (size_t)grp * 3 * kStride;
+    const int N = a.sys[wi.sys[wi.slot[wave]]].n_beads;
+    const double *P = a.pos + (size_t)(w0 + grp) * 3 * a.npad;
+    for (int j = threadIdx.x & (G - 1); j < kStride; j += G) {
+        mine[j] = j < N ? P[j] : 0.0;
+        mine[kStride + j] = j < N ? P[a.npad + j] : 0.0;
+        mine[2 * kStride + j] = j < N ? P[2 * a.npad + j] : 0.0;
+    }
+}
+
+struct PairShared {
+    const void *kc, *angc;
+    const double *ctab;
+    double *lw;
+    unsigned int *hist;
+    const int *binfo;
+    double *coord;           // wave slabs of kSlabCoord doubles
+    Staged *sq;              // wave slabs of kSlabStage entries
+    int2 *sb;
+    int slab_coord, slab_stage;
+};
+
+template <bool FP64, int G, int SLOTS, bool PERIODIC, bool CHAIN>
+__device__ void pair_wave(const SweepArgs &a, const WorkItem &wi, int wave, const PairShared &sh,
+                          long long n_sweeps) {
+    constexpr int kStage = G + 1;   // staged moves per walker (+1 spare for the prefetch)
+    constexpr int kStride = G * SLOTS;
+    const int w0 = wi.walker[wave];
+    if (w0 < 0) return;
+    const int grp = (threadIdx.x & 63) / G;
+    const int i = wi.slot[wave];
+    const SysDev &sd = a.sys[wi.sys[i]];
+    double *mine = sh.coord + (size_t)wave * sh.slab_coord + (size_t)grp * 3 * kStride;
+    PairLds L;
+    L.lw = sh.lw + wi.lds_off[i] + i;
+    L.hist = sh.hist + wi.lds_off[i];
+    L.binfo = sh.binfo + i * kMaxBeads;
+    L.x = mine;
+    L.y = mine + kStride;
+    L.z = mine + 2 * kStride;
+    L.ctab = sh.ctab;
+    L.kc = sh.kc;
+    L.angc = sh.angc;
+    L.sb = sh.sb + (size_t)wave * sh.slab_stage + grp * kStage;
+    L.sq = sh.sq + (size_t)wave * sh.slab_stage + grp * kStage;
+    run_pair<FP64, G, SLOTS, PERIODIC, CHAIN>(a, sd, w0 + grp, L, n_sweeps);
+}
+
 // LDS layout (per workgroup), 16-byte items first: the {kappa, kappa C_LJ} table (intra, inter)
-// in the accumulator type; the bending / torsion coefficient table; the staged draws of every
-// walker; the C_LJ table; the coordinate mirror of every walker (x, y, z blocks of pos_stride =
-// G * SLOTS doubles each, so one address with constant offsets reaches all three, zeros past the
-// last bead); ln W at the bin edges of every system of the workgroup (system i at
-// lds_off[i] + i); the staged bead indices and descriptors of every walker; the 32-bit
-// histograms (system i at lds_off[i]); the bead descriptors of every system.
+// in the accumulator type; the bending / torsion coefficient table; the staged draws (one slab
+// per wave); the C_LJ table; the coordinate mirrors (one slab per wave); ln W at the bin edges of
+// every system of the workgroup (system i at lds_off[i] + i); the staged bead indices and
+// descriptors (one slab per wave); the 32-bit histograms (system i at lds_off[i]); the bead
+// descriptors of every system.
+// G > 0: every wave holds 64 / G walkers in groups of G lanes with SLOTS bead slots per lane.
+// G = 0 (mixed plan): wave v holds walkers of lanes-per-walker wi.kind[v], with the slots fixed
+// per kind (16 lanes: 2 slots, at most 32 beads; 32 lanes: 2 slots; 64 lanes: 1 slot), so long
+// chains can run one walker per wave while short ones share a wave four at a time.
 template <bool FP64, int G, int SLOTS, bool PERIODIC, bool CHAIN>
 __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_sweeps) {
-    constexpr int kStage = G + 1;   // staged moves per walker (+1 spare for the prefetch)
-    constexpr int kPer = 64 / G;    // walkers per wave
-    constexpr int kStride = G * SLOTS;
+    constexpr int kSlabStage = pair_slab_stage(G);
+    constexpr int kSlabCoord = pair_slab_coord(G, SLOTS);
     using A = AccP<FP64>;
     using A2 = typename std::conditional<FP64, double2, float2>::type;
     extern __shared__ double2 lds_p[];
     const WorkItem &wi = a.work[blockIdx.x];
     const int ns = wi.n_sys;
     const int n_waves = blockDim.x >> 6;
-    const int n_wl = kPer * n_waves;
     const int bins_total = wi.lds_off[ns - 1] + a.sys[wi.sys[ns - 1]].n_bins;
     A2 *kc = reinterpret_cast<A2 *>(lds_p);
     A *angc = reinterpret_cast<A *>(lds_p + 2 * kMaxTypes * kMaxTypes);
     Staged *sq = reinterpret_cast<Staged *>(lds_p + 2 * kMaxTypes * kMaxTypes + kAngcEntries / 2);
-    double *ctab = reinterpret_cast<double *>(sq + (size_t)n_wl * kStage);
+    double *ctab = reinterpret_cast<double *>(sq + (size_t)n_waves * kSlabStage);
     double *pc = ctab + kMaxTypes * kMaxTypes;
-    double *lw = pc + (size_t)n_wl * 3 * kStride;
+    double *lw = pc + (size_t)n_waves * kSlabCoord;
     int2 *sb = reinterpret_cast<int2 *>(lw + bins_total + ns);
-    unsigned int *hist = reinterpret_cast<unsigned int *>(sb + n_wl * kStage);
+    unsigned int *hist = reinterpret_cast<unsigned int *>(sb + (size_t)n_waves * kSlabStage);
     int *binfo = reinterpret_cast<int *>(hist + bins_total);
     for (int i = 0; i < ns; ++i) {
         const SysDev &sd = a.sys[wi.sys[i]];
@@ -833,37 +904,27 @@ __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_swe
         angc[threadIdx.x] = c;
     }
     const int wave = threadIdx.x >> 6;
-    const int grp = (threadIdx.x & 63) / G;
-    const int w0 = wi.walker[wave];
-    const int wl = kPer * wave + grp;
-    double *mine = pc + (size_t)wl * 3 * kStride;
-    if (w0 >= 0) {                  // coordinate mirror of this group's walker
-        const int N = a.sys[wi.sys[wi.slot[wave]]].n_beads;
-        const double *P = a.pos + (size_t)(w0 + grp) * 3 * a.npad;
-        for (int j = threadIdx.x & (G - 1); j < kStride; j += G) {
-            mine[j] = j < N ? P[j] : 0.0;
-            mine[kStride + j] = j < N ? P[a.npad + j] : 0.0;
-            mine[2 * kStride + j] = j < N ? P[2 * a.npad + j] : 0.0;
-        }
+    double *slab = pc + (size_t)wave * kSlabCoord;
+    if constexpr (G > 0) {
+        pair_mirror<G, SLOTS>(a, wi, wave, slab);
+    } else {
+        const int kind = wi.kind[wave];
+        if (kind == 64) pair_mirror<64, 1>(a, wi, wave, slab);
+        else if (kind == 32) pair_mirror<32, 2>(a, wi, wave, slab);
+        else if (kind == 16) pair_mirror<16, 2>(a, wi, wave, slab);
     }
     __syncthreads();
-    if (w0 >= 0) {
-        const int i = wi.slot[wave];
-        const int sys = wi.sys[i];
-        const SysDev &sd = a.sys[sys];
-        PairLds L;
-        L.lw = lw + wi.lds_off[i] + i;
-        L.hist = hist + wi.lds_off[i];
-        L.binfo = binfo + i * kMaxBeads;
-        L.x = mine;
-        L.y = mine + kStride;
-        L.z = mine + 2 * kStride;
-        L.ctab = ctab;
-        L.kc = kc;
-        L.angc = angc;
-        L.sb = sb + wl * kStage;
-        L.sq = sq + (size_t)wl * kStage;
-        run_pair<FP64, G, SLOTS, PERIODIC, CHAIN>(a, sd, w0 + grp, L, n_sweeps);
+    PairShared sh;
+    sh.kc = kc; sh.angc = angc; sh.ctab = ctab; sh.lw = lw; sh.hist = hist; sh.binfo = binfo;
+    sh.coord = pc; sh.sq = sq; sh.sb = sb;
+    sh.slab_coord = kSlabCoord; sh.slab_stage = kSlabStage;
+    if constexpr (G > 0) {
+        pair_wave<FP64, G, SLOTS, PERIODIC, CHAIN>(a, wi, wave, sh, n_sweeps);
+    } else {
+        const int kind = wi.kind[wave];
+        if (kind == 64) pair_wave<FP64, 64, 1, PERIODIC, CHAIN>(a, wi, wave, sh, n_sweeps);
+        else if (kind == 32) pair_wave<FP64, 32, 2, PERIODIC, CHAIN>(a, wi, wave, sh, n_sweeps);
+        else if (kind == 16) pair_wave<FP64, 16, 2, PERIODIC, CHAIN>(a, wi, wave, sh, n_sweeps);
     }
     __syncthreads();
     for (int i = 0; i < ns; ++i) {
@@ -878,9 +939,8 @@ __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_swe
 
 template <bool FP64, int G, int SLOTS, bool PERIODIC, bool CHAIN>
 static hipError_t launch_pair_t(const SweepArgs &a, int n_items, int waves, size_t lds,
-                                long long n_sweeps, int pos_stride, hipStream_t st) {
-    // __launch_bounds__(512); the LDS size was computed for this coordinate stride
-    if (waves < 1 || waves > 8 || pos_stride != G * SLOTS) return hipErrorInvalidValue;
+                                long long n_sweeps, hipStream_t st) {
+    if (waves < 1 || waves > 8) return hipErrorInvalidValue;   // __launch_bounds__(512)
     auto kern = k_sweep_pair<FP64, G, SLOTS, PERIODIC, CHAIN>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -891,23 +951,25 @@ static hipError_t launch_pair_t(const SweepArgs &a, int n_items, int waves, size
 
 template <bool FP64, bool PERIODIC, int G, bool CHAIN>
 static hipError_t launch_pair_s(const SweepArgs &a, int slots, int n_items, int waves, size_t lds,
-                                long long n_sweeps, int pos_stride, hipStream_t st) {
+                                long long n_sweeps, hipStream_t st) {
     switch (slots) {
-        case 1: return launch_pair_t<FP64, G, 1, PERIODIC, CHAIN>(a, n_items, waves, lds, n_sweeps, pos_stride, st);
-        case 2: return launch_pair_t<FP64, G, 2, PERIODIC, CHAIN>(a, n_items, waves, lds, n_sweeps, pos_stride, st);
-        case 3: return launch_pair_t<FP64, G, 3, PERIODIC, CHAIN>(a, n_items, waves, lds, n_sweeps, pos_stride, st);
-        case 4: return launch_pair_t<FP64, G, 4, PERIODIC, CHAIN>(a, n_items, waves, lds, n_sweeps, pos_stride, st);
+        case 1: return launch_pair_t<FP64, G, 1, PERIODIC, CHAIN>(a, n_items, waves, lds, n_sweeps, st);
+        case 2: return launch_pair_t<FP64, G, 2, PERIODIC, CHAIN>(a, n_items, waves, lds, n_sweeps, st);
+        case 3: return launch_pair_t<FP64, G, 3, PERIODIC, CHAIN>(a, n_items, waves, lds, n_sweeps, st);
+        case 4: return launch_pair_t<FP64, G, 4, PERIODIC, CHAIN>(a, n_items, waves, lds, n_sweeps, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <bool FP64, bool PERIODIC, bool CHAIN>
 static hipError_t launch_pair_g(const SweepArgs &a, int group, int slots, int n_items, int waves,
-                                size_t lds, long long n_sweeps, int pos_stride, hipStream_t st) {
+                                size_t lds, long long n_sweeps, hipStream_t st) {
     if (group == 16)
-        return launch_pair_s<FP64, PERIODIC, 16, CHAIN>(a, slots, n_items, waves, lds, n_sweeps, pos_stride, st);
+        return launch_pair_s<FP64, PERIODIC, 16, CHAIN>(a, slots, n_items, waves, lds, n_sweeps, st);
     if (group == 32)
-        return launch_pair_s<FP64, PERIODIC, 32, CHAIN>(a, slots, n_items, waves, lds, n_sweeps, pos_stride, st);
+        return launch_pair_s<FP64, PERIODIC, 32, CHAIN>(a, slots, n_items, waves, lds, n_sweeps, st);
+    if (group == 0)
+        return launch_pair_t<FP64, 0, 0, PERIODIC, CHAIN>(a, n_items, waves, lds, n_sweeps, st);
     return hipErrorInvalidValue;
 }
 
@@ -915,12 +977,12 @@ static hipError_t launch_pair_g(const SweepArgs &a, int group, int slots, int n_
 template <bool CHAIN>
 static hipError_t launch_pair_all(const SweepArgs &a, bool fp64, int group, int slots,
                                   bool periodic, int n_items, int waves, size_t lds,
-                                  long long n_sweeps, int pos_stride, hipStream_t st) {
+                                  long long n_sweeps, hipStream_t st) {
     if (fp64)
-        return periodic ? launch_pair_g<true, true, CHAIN>(a, group, slots, n_items, waves, lds, n_sweeps, pos_stride, st)
-                        : launch_pair_g<true, false, CHAIN>(a, group, slots, n_items, waves, lds, n_sweeps, pos_stride, st);
-    return periodic ? launch_pair_g<false, true, CHAIN>(a, group, slots, n_items, waves, lds, n_sweeps, pos_stride, st)
-                    : launch_pair_g<false, false, CHAIN>(a, group, slots, n_items, waves, lds, n_sweeps, pos_stride, st);
+        return periodic ? launch_pair_g<true, true, CHAIN>(a, group, slots, n_items, waves, lds, n_sweeps, st)
+                        : launch_pair_g<true, false, CHAIN>(a, group, slots, n_items, waves, lds, n_sweeps, st);
+    return periodic ? launch_pair_g<false, true, CHAIN>(a, group, slots, n_items, waves, lds, n_sweeps, st)
+                    : launch_pair_g<false, false, CHAIN>(a, group, slots, n_items, waves, lds, n_sweeps, st);
 }
 
 }  // namespace muca

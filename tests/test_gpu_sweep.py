@@ -165,6 +165,41 @@ def test_fp64_paper_systems(lib, orc, name, pack):
     _compare(lib, orc, wl, walkers=_walkers(pack, 4), n_sweeps=300, pack=pack)
 
 
+# Mixed plan (walkers_per_wave = -1): per system 16 lanes per walker (N <= 16, or short chains
+# moved there to make room), 32, or a whole wave for the longest chains (N >= 0.8 N_max);
+# launch_info()["lanes_used"] has bit 0, 1, 2 for 16, 32, 64 lanes.
+@pytest.mark.parametrize("make,lanes", [
+    (lambda: workloads.chains_of_lengths([12, 24, 40, 56]), 0b111),      # all three kinds
+    (lambda: workloads.chains_of_lengths([64, 3, 33]), 0b111),           # extremes, ragged slots
+    (lambda: workloads.aggregation(), 0b100),                            # periodic, rigid moves
+])
+def test_fp64_mixed_plan(lib, orc, make, lanes):
+    wl = make()
+    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=4, precision=0,
+                               walkers_per_wave=-1)
+    assert m.launch_info()["lanes_used"] == lanes
+    m.close()
+    _compare(lib, orc, wl, walkers=8, n_sweeps=300, pack=-1)
+
+
+def test_fp64_mixed_plan_chain_moves(lib, orc):
+    """The human cross-seeding mixture (38 beads, one walker per wave) in its sphere with
+    rigid translations, pivots and chain rotations."""
+    wl = workloads.paper_system("cross_human", walkers=4)
+    _compare(lib, orc, wl, walkers=4, n_sweeps=200, pack=-1)
+
+
+def test_mixed_plan_limits(lib):
+    """The mixed plan needs walkers per system in multiples of 4, at most 64 beads, and a chain
+    long enough to gain from a whole wave."""
+    for wl, kw in ((workloads.single_chain(), dict(walkers=6)),              # 6 % 4 != 0
+                   (workloads.cross_seeding(walkers=4), dict(walkers=4)),     # 76 beads
+                   (workloads.chains_of_lengths([12, 16]), dict(walkers=4))):  # all short
+        with pytest.raises(lib.MucaError) as ei:
+            lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers_per_wave=-1, **kw)
+        assert "INVAL" in str(ei.value)
+
+
 def test_chain_moves_need_several_walkers_per_wave(lib):
     import dataclasses
     wl = dataclasses.replace(workloads.single_chain(), pivot_per_sweep=1)

@@ -158,6 +158,16 @@ def batched_chains(seed: int = 1702, n_seq: int = 32, n_min: int = 13, n_max: in
                     n_iter=n_iter, n_sweeps=n_sweeps)
 
 
+def chains_of_lengths(lengths, seed: int = 1702, walkers: int = 4,
+                      precision: int = PREC_FP64) -> Workload:
+    """Single-chain systems of the given lengths (seeded A/B sequences), `walkers` per system."""
+    rng = np.random.default_rng([seed, 7])
+    systems = [_single_chain_system(ab_sequence(rng, int(n)), 0.05) for n in lengths]
+    return Workload(name="chains_" + "_".join(str(int(n)) for n in lengths), systems=systems,
+                    walkers_per_system=walkers, precision=precision, seed=seed,
+                    resync_sweeps=100 if precision == PREC_FP32_SPLIT else 0)
+
+
 def aggregation(seed: int = 1702, walkers: int = 1024, precision: int = PREC_FP32_SPLIT,
                 n_iter: int = 10, n_sweeps: int = 10000) -> Workload:
     """Four identical 9-bead chains in a periodic cube of edge 20, intra + inter LJ."""
