@@ -61,7 +61,8 @@ def run_gpu(wl, walkers, n_sweeps, steps, warmup, stream, autotune=True, **launc
     import workloads
     m = P.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=walkers,
                              stream=stream.cuda_stream, **launch)
-    chosen = m.autotune(probe_sweeps=max(5, n_sweeps // 200)) if autotune else None
+    # probes of a fixed length, so that the plan does not depend on the sweeps per iteration
+    chosen = m.autotune(probe_sweeps=min(500, max(5, n_sweeps))) if autotune else None
     plan = m.launch_info()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)

@@ -161,8 +161,10 @@ static int build_schedule(muca_ctx *ctx, int wpb, bool pair, int pack);
 // longest first, while that still shortens the slowest sweep (N >= 0.8 N_max); every such system
 // needs W / 2 more waves, made up by moving the shortest chains (N <= 32) to four walkers per
 // wave, so that all waves stay resident (8 per CU); chains of at most 16 beads always run four
-// per wave.  Fails when no system would move.
-static int plan_mixed(muca_ctx *ctx) {
+// per wave.  At most max64 systems move to whole waves (two waves on one SIMD share its issue
+// slots, so moving fewer can be faster; the autotuner tries several).  Fails when no system
+// would move.
+static int plan_mixed(muca_ctx *ctx, int max64) {
     const int n = ctx->n_sys, W = ctx->W;
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
@@ -171,7 +173,7 @@ static int plan_mixed(muca_ctx *ctx) {
     });
     const int budget = 8 * std::max(1, ctx->n_cu);
     const int nmax = ctx->sys[order[0]].n_beads;
-    for (int n64 = n; n64 >= 1; --n64) {
+    for (int n64 = std::min(n, max64); n64 >= 1; --n64) {
         // chains of at most 16 beads fill one slot of 16 lanes: four walkers per wave cost them
         // nothing
         std::vector<int> kind(n, 32);
@@ -704,7 +706,7 @@ int muca_init(const muca_config *cfg, muca_ctx **out) {
             ctx->err = "the mixed plan needs at most 64 beads per system";
             return bail(MUCA_E_INVAL);
         }
-        rc = plan_mixed(ctx);
+        rc = plan_mixed(ctx, ctx->n_sys);
         if (rc != MUCA_OK) return bail(rc);
         *out = ctx;
         return MUCA_OK;
@@ -1133,7 +1135,7 @@ int muca_autotune(muca_ctx *ctx, int64_t probe_sweeps, int32_t *chosen) {
     std::vector<char> saved(bytes);
     rc = muca_get_state(ctx, saved.data(), &bytes);
     if (rc != MUCA_OK) return rc;
-    struct Cand { int pack, wpb; bool pair; };
+    struct Cand { int pack, wpb; bool pair; int max64; };
     std::vector<Cand> cands;
     for (int pack : {4, 2, 1}) {
         if (!pack_ok(ctx, pack)) continue;
@@ -1142,17 +1144,23 @@ int muca_autotune(muca_ctx *ctx, int64_t probe_sweeps, int32_t *chosen) {
                 if (pack > 1 && c > 8) continue;
                 if (c * pack > ctx->W) continue;
                 if (!pr && (ctx->n_sys == 1 || c < 8)) continue;   // pairing makes no difference
-                cands.push_back(Cand{pack, c, pr != 0});
+                cands.push_back(Cand{pack, c, pr != 0, 0});
             }
     }
-    if (pack_ok(ctx, kPackMixed)) cands.push_back(Cand{kPackMixed, 8, true});
-    Cand best{ctx->pack, ctx->wpb, ctx->paired};
+    if (pack_ok(ctx, kPackMixed)) {
+        // at most 1, 2, 3, 4, 6, 8 or all systems on whole waves
+        for (int m64 : {1, 2, 3, 4, 6, 8})
+            if (m64 < ctx->n_sys) cands.push_back(Cand{kPackMixed, 8, true, m64});
+        cands.push_back(Cand{kPackMixed, 8, true, ctx->n_sys});
+    }
+    Cand best{ctx->pack, ctx->wpb, ctx->paired, ctx->n_sys};
     float best_ms = 1e30f;
     hipEvent_t e0, e1;
     CK(hipEventCreate(&e0));
     CK(hipEventCreate(&e1));
     for (const Cand &cd : cands) {
-        rc = cd.pack == kPackMixed ? plan_mixed(ctx) : build_schedule(ctx, cd.wpb, cd.pair, cd.pack);
+        rc = cd.pack == kPackMixed ? plan_mixed(ctx, cd.max64)
+                                   : build_schedule(ctx, cd.wpb, cd.pair, cd.pack);
         if (rc == MUCA_E_INVAL) { rc = MUCA_OK; continue; }   // does not fit in LDS
         if (rc != MUCA_OK) break;
         rc = launch_chunked(ctx, 1);                 // warm the code path
@@ -1164,9 +1172,10 @@ int muca_autotune(muca_ctx *ctx, int64_t probe_sweeps, int32_t *chosen) {
         CK(hipEventSynchronize(e1));
         float ms = 0.f;
         CK(hipEventElapsedTime(&ms, e0, e1));
-        // the mixed plan is tried last and kept only when clearly faster (3 %), so that near
-        // ties keep the uniform plan
-        const float need = cd.pack == kPackMixed ? 0.97f * best_ms : best_ms;
+        // mixed plans are tried last and replace a uniform plan only when faster by more than
+        // 1 %, so that near ties keep the uniform plan
+        const float need = (cd.pack == kPackMixed && best.pack != kPackMixed) ? 0.99f * best_ms
+                                                                               : best_ms;
         if (ms < need) { best_ms = ms; best = cd; }
         rc = muca_set_state(ctx, saved.data(), bytes);
         if (rc != MUCA_OK) break;
@@ -1176,7 +1185,8 @@ int muca_autotune(muca_ctx *ctx, int64_t probe_sweeps, int32_t *chosen) {
     if (rc != MUCA_OK) return rc;
     rc = sync_and_check(ctx);
     if (rc != MUCA_OK) return rc;
-    rc = best.pack == kPackMixed ? plan_mixed(ctx) : build_schedule(ctx, best.wpb, best.pair, best.pack);
+    rc = best.pack == kPackMixed ? plan_mixed(ctx, best.max64)
+                                 : build_schedule(ctx, best.wpb, best.pair, best.pack);
     if (rc != MUCA_OK) return rc;
     ctx->err.clear();
     if (chosen) *chosen = best.pair ? best.wpb : -best.wpb;

@@ -332,11 +332,17 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
         for (int i = 0; i < nblk; ++i) {
             // everything read here depends only on the staged draw of this move, so all of it is
             // in flight at once; the draw of the next move is read now as well
+            // the proposal's inputs (neighbours, moved bead, draws) are requested first, the
+            // pair loop's (this lane's beads, couplings) behind them
             const int b = bi_nx.x, infb = bi_nx.y;
+            const bool fst = bi_first(infb), lst = bi_last(infb);
+            const int bm = fst ? b : b - 1, bp = lst ? b : b + 1;
+            const double xmx = L.x[bm], xmy = L.y[bm], xmz = L.z[bm];
+            const double xpx = L.x[bp], xpy = L.y[bp], xpz = L.z[bp];
+            const double xbx = L.x[b], xby = L.y[b], xbz = L.z[b];
             const Staged q = L.sq[i];
             bi_nx = L.sb[i + 1];
             const int tb = bi_type(infb), cb = bi_chain(infb);
-            const bool fst = bi_first(infb), lst = bi_last(infb);
             // coupling of every slot's bead with b, and the coefficient of u_j . m for
             // j = b-3 .. b+2 of the same chain (0 elsewhere: entry 6)
             const A *act = reinterpret_cast<const A *>(L.angc) + (fst ? 8 : 0) + (lst ? 16 : 0);
@@ -351,10 +357,6 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 const unsigned ai = min((unsigned)(gl + G * s - b + 3), 6u);
                 coef[s] = act[same ? ai : 6u];
             }
-            const int bm = fst ? b : b - 1, bp = lst ? b : b + 1;
-            const double xbx = L.x[b], xby = L.y[b], xbz = L.z[b];
-            const double xmx = L.x[bm], xmy = L.y[bm], xmz = L.z[bm];
-            const double xpx = L.x[bp], xpy = L.y[bp], xpz = L.z[bp];
             double nx, ny, nz;
             if (fst || lst) {
                 // end bead: new bond along (x_b - x_a) + rho g, unit length, from anchor a
@@ -425,7 +427,9 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             const int kn = inwin ? (int)t : 0;
             const double lnw_new = lnw_at(L.lw, kn, t);
             // steric sphere: a bead may not leave it
-            const bool inside = a.sphere_r2 <= 0.0 || nx * nx + ny * ny + nz * nz <= a.sphere_r2;
+            bool inside = true;
+            if (__builtin_expect(a.sphere_r2 > 0.0, 0))
+                inside = nx * nx + ny * ny + nz * nz <= a.sphere_r2;
             const bool accept = inwin && inside && (q.lnu < lnw_new - lnw_cur);
             n_wrej += inwin ? 0u : 1u;
             if (alog && (long long)n_mv < a.acc_log_moves && accept && gl == 0)
