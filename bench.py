@@ -25,6 +25,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (published, packed)
+# wave64 VALU instructions the chip can issue per second: 256 CUs x 4 SIMDs, one instruction
+# every 4 cycles per SIMD (64 lanes on 16-wide units) at 2.4 GHz
+PEAK_VALU_INSTS = 256 * 4 * 2.4e9 / 4
 
 
 def algorithmic_flops_per_move(n_beads: int, n_chains: int = 1, periodic: bool = False,
@@ -473,9 +476,9 @@ def copy_calibration(n_mib: int = 512, reps: int = 3):
     return n_mib
 
 
-def sweep_traffic():
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary, or None when the
-    sweep kernel sources changed since the counters were taken."""
+def sweep_counters():
+    """The committed rocprofv3 counter record of the sweep launch (HBM bytes, VALU instructions
+    per launch), or None when the sweep kernel sources changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "sweep_traffic.json")
     if not os.path.exists(path):
@@ -486,7 +489,13 @@ def sweep_traffic():
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if h.hexdigest() != rec.get("sources_sha256"):
         return None
-    return rec["bytes_per_launch"]
+    return rec
+
+
+def sweep_traffic():
+    """HBM bytes per sweep launch from the committed counter record, or None (see above)."""
+    rec = sweep_counters()
+    return rec["bytes_per_launch"] if rec else None
 
 
 def main():
@@ -569,6 +578,14 @@ def main():
         "acceptance": r["acc_rate"],
         "wall_s": r["wall_s"],
     }
+    rec = sweep_counters()
+    if rec and rec.get("valu_insts_per_launch"):
+        # issue-rate view of the same launches: profiled wave instructions per launch over the
+        # launch time measured here
+        rate = rec["valu_insts_per_launch"] / (out["sweep_launch"]["avg_ms"] / 1e3)
+        out["valu_issue"] = {"insts_per_launch": rec["valu_insts_per_launch"],
+                             "achieved_per_s": rate, "peak_per_s": PEAK_VALU_INSTS,
+                             "frac": rate / PEAK_VALU_INSTS}
     if not args.no_plain:
         rp = run_gpu(wl, 1, args.plain_sweeps, 1, 0, st, autotune=False)
         plain = rp["moves"] / (rp["event_ms"] / 1e3)
