@@ -10,8 +10,11 @@
 //
 // One wave per walker, lane j holds bead j (at most 64 beads): position, vector, momentum.
 // Positions are segmented prefix sums of the vectors and generalized forces segmented suffix
-// sums of the bead forces (shuffle scans within each chain); energies and forces in FP64, the
-// pair loop over all beads per lane, angle terms once per lane and gathered through LDS.
+// sums of the bead forces (shuffle scans within each chain); energies and forces in FP64.  Every
+// unordered pair is evaluated once: at offset d = 1 .. N/2 lane j takes the pair (j, j + d mod N)
+// (for even N the pairs at d = N/2 only on the lower half) and adds the reaction force to the
+// partner's LDS accumulator, in the same order on every call; angle terms once per lane,
+// gathered through LDS.
 #include "muca_internal.h"
 
 namespace muca {
@@ -20,6 +23,7 @@ constexpr int kHmcWaves = 4;   // walkers per workgroup
 
 struct HmcLds {
     double x[64], y[64], z[64];
+    double rx[64], ry[64], rz[64];          // reaction forces of the pair loop
     double bp[64][3], bq[64][3], tp[64][3], tq[64][3];
 };
 
@@ -39,6 +43,14 @@ __device__ __forceinline__ double seg_suffix(double v, int lane, int ce) {
     return v;
 }
 
+// 1 / x for a positive normal x: the hardware estimate refined by two Newton steps
+// y <- y + y (1 - x y), which leave the error at the rounding level of FP64.
+__device__ __forceinline__ double recip(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+
 // Derivative of kappa (1 - p.q / (|p||q|)) with respect to the bonds p and q; returns 1 - cos.
 __device__ __forceinline__ double angle_grad(const double p[3], const double q[3], double kappa,
                                              double dp[3], double dq[3]) {
@@ -54,35 +66,49 @@ __device__ __forceinline__ double angle_grad(const double p[3], const double q[3
     return 1.0 - cs;
 }
 
-// Energy (wave-uniform) and this lane's dE/dx for the positions in L.
+// Energy (wave-uniform) and this lane's dE/dx for the positions in L; ct = {kappa, kappa C_LJ}
+// per (intra / inter, type, type).
 template <bool PERIODIC>
-__device__ double energy_forces(const SweepArgs &a, HmcLds &L, const int *bi, int N, int lane,
-                                int ce, double &gx, double &gy, double &gz) {
+__device__ double energy_forces(const SweepArgs &a, HmcLds &L, const int *bi, const double2 *ct,
+                                int N, int lane, int ce, double &gx, double &gy, double &gz) {
     const bool act = lane < N;
     double e = 0.0;
     gx = gy = gz = 0.0;
     const double xj = L.x[act ? lane : 0], yj = L.y[act ? lane : 0], zj = L.z[act ? lane : 0];
-    if (act) {
-        const int infj = bi[lane], tj = bi_type(infj), cj = bi_chain(infj);
-        for (int i = 0; i < N; ++i) {
-            const int infi = bi[i];
-            const bool same = bi_chain(infi) == cj;
-            if (i == lane || (same && (i == lane - 1 || i == lane + 1))) continue;
-            double dx = xj - L.x[i], dy = yj - L.y[i], dz = zj - L.z[i];
-            if constexpr (PERIODIC) {
-                dx -= a.box_len * rint(dx * a.inv_box);
-                dy -= a.box_len * rint(dy * a.inv_box);
-                dz -= a.box_len * rint(dz * a.inv_box);
-            }
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            const double s = 1.0 / r2, s3 = s * s * s;
-            const double kap = same ? a.k_intra : a.k_inter;
-            const double cc = a.c_lj[tj * a.n_types + bi_type(infi)];
-            e += 0.5 * kap * s3 * (s3 - cc);
-            const double f = kap * (-12.0 * s3 + 6.0 * cc) * s3 * s;
-            gx += f * dx; gy += f * dy; gz += f * dz;
+    L.rx[lane] = 0.0; L.ry[lane] = 0.0; L.rz[lane] = 0.0;
+    __builtin_amdgcn_wave_barrier();
+    const int infj = bi[lane], tj = bi_type(infj), cj = bi_chain(infj);
+    const int dmax = N / 2;
+    for (int d = 1; d <= dmax; ++d) {
+        int i = lane + d;
+        if (i >= N) i -= N;
+        const int infi = bi[i];
+        const bool same = bi_chain(infi) == cj;
+        // bonded neighbours (i = j + 1 in one chain), lanes past the beads, and the second copy
+        // of each pair at d = N/2 when N is even
+        const bool use = act && !(same && d == 1 && i == lane + 1) &&
+                         !(2 * d == N && lane >= dmax);
+        double dx = xj - L.x[i], dy = yj - L.y[i], dz = zj - L.z[i];
+        if constexpr (PERIODIC) {
+            dx -= a.box_len * rint(dx * a.inv_box);
+            dy -= a.box_len * rint(dy * a.inv_box);
+            dz -= a.box_len * rint(dz * a.inv_box);
         }
+        const double r2 = use ? dx * dx + dy * dy + dz * dz : 1.0;
+        const double s = recip(r2), s3 = s * s * s;
+        const double2 kc = ct[(same ? 0 : kMaxTypes * kMaxTypes) + tj * kMaxTypes + bi_type(infi)];
+        const double ep = s3 * (kc.x * s3 - kc.y);
+        const double f = use ? (-12.0 * kc.x * s3 + 6.0 * kc.y) * s3 * s : 0.0;
+        e += use ? ep : 0.0;
+        const double fx = f * dx, fy = f * dy, fz = f * dz;
+        gx += fx; gy += fy; gz += fz;
+        // lanes of one offset hit distinct partners: no two adds to one address at once
+        atomicAdd(&L.rx[i], -fx);
+        atomicAdd(&L.ry[i], -fy);
+        atomicAdd(&L.rz[i], -fz);
     }
+    __builtin_amdgcn_wave_barrier();
+    gx += L.rx[lane]; gy += L.ry[lane]; gz += L.rz[lane];
     // bending (beads j, j+1, j+2) and torsion-like (j .. j+3) terms of this lane
     double dp[3] = {0, 0, 0}, dq[3] = {0, 0, 0}, ep[3] = {0, 0, 0}, eq[3] = {0, 0, 0};
     if (act && lane + 2 <= ce) {
@@ -129,9 +155,18 @@ template <bool PERIODIC>
 __global__ void __launch_bounds__(64 * kHmcWaves) k_hmc(SweepArgs a, HmcArgs h) {
     __shared__ HmcLds lds[kHmcWaves];
     __shared__ int bis[kHmcWaves][64];
+    __shared__ double2 ct[2 * kMaxTypes * kMaxTypes];
+    if (threadIdx.x < 2 * kMaxTypes * kMaxTypes) {
+        const int e = threadIdx.x % (kMaxTypes * kMaxTypes);
+        const int t = e / kMaxTypes, u = e % kMaxTypes;
+        const double c = (t < a.n_types && u < a.n_types) ? a.c_lj[t * a.n_types + u] : 0.0;
+        const double kap = threadIdx.x < kMaxTypes * kMaxTypes ? a.k_intra : a.k_inter;
+        ct[threadIdx.x] = make_double2(kap, kap * c);
+    }
+    __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int w = blockIdx.x * kHmcWaves + wave;
-    if (w >= h.n_walkers) return;                 // no workgroup barrier below
+    if (w >= h.n_walkers) return;                 // no workgroup barrier below this one
     HmcLds &L = lds[wave];
     int *bi = bis[wave];
     const int sys = h.walker_sys[w];
@@ -174,7 +209,7 @@ __global__ void __launch_bounds__(64 * kHmcWaves) k_hmc(SweepArgs a, HmcArgs h) 
                           0.5 * wave_sum_d(mx * mx + my * my + mz * mz);
         // forces at the start
         double gx, gy, gz;
-        double Ec = energy_forces<PERIODIC>(a, L, bi, N, lane, ce, gx, gy, gz);
+        double Ec = energy_forces<PERIODIC>(a, L, bi, ct, N, lane, ce, gx, gy, gz);
         auto gen_forces = [&](double Ecur, double &Gx, double &Gy, double &Gz) {
             const double b = beta[bin_of(Ecur, e_lo, eps, K)];
             Gx = seg_suffix(-b * gx, lane, ce);
@@ -217,7 +252,7 @@ __global__ void __launch_bounds__(64 * kHmcWaves) k_hmc(SweepArgs a, HmcArgs h) 
             nz = seg_prefix(vz, lane, cs);
             L.x[lane] = nx; L.y[lane] = ny; L.z[lane] = nz;
             __builtin_amdgcn_wave_barrier();
-            Ec = energy_forces<PERIODIC>(a, L, bi, N, lane, ce, gx, gy, gz);
+            Ec = energy_forces<PERIODIC>(a, L, bi, ct, N, lane, ce, gx, gy, gz);
             gen_forces(Ec, Gx, Gy, Gz);
             kick(0.5 * hs);
         }

