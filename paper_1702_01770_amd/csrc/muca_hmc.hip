@@ -151,8 +151,11 @@ __device__ __forceinline__ int bin_of(double e, double e_lo, double eps, int K) 
     return t >= (double)K ? K - 1 : (int)t;
 }
 
+// At least four waves per SIMD (128 VGPRs; the compiler spills a few FP64 values outside the
+// pair loop): the 4096 walkers of the batched workload are then resident at once, which beats
+// two rounds at 195 registers (2.27 vs 2.61 ms for its 10 x 10-step trajectories).
 template <bool PERIODIC>
-__global__ void __launch_bounds__(64 * kHmcWaves) k_hmc(SweepArgs a, HmcArgs h) {
+__global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs h) {
     __shared__ HmcLds lds[kHmcWaves];
     __shared__ int bis[kHmcWaves][64];
     __shared__ double2 ct[2 * kMaxTypes * kMaxTypes];
