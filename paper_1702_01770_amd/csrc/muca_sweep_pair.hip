@@ -1,12 +1,14 @@
 // Multicanonical Metropolis sweep, several walkers per wavefront (CDNA4, gfx950).
 //
 // Same algorithm and random streams as k_sweep (muca_sweep.hip); this variant packs 64 / G
-// walkers of one system into a wave, G = 32 or 16 lanes each (a group), so the serial part of a
-// trial move (proposal, acceptance test, bookkeeping) is shared by two or four Markov chains.
-// Bead j of a walker lives in lane (j mod G) of its group, slot j / G.  Values that are uniform
-// within a group (bead index, energy, bin, ...) are plain VGPRs.  Coordinates are mirrored in
-// LDS so that each group can read "its" moved bead and neighbours with ordinary LDS loads; every
-// update of a bead is written by all lanes of its group.
+// walkers of one system into a wave, G = 16, 32 or 64 lanes each (a group), so the serial part of
+// a trial move (proposal, acceptance test, bookkeeping) is shared by up to four Markov chains; the
+// mixed instance (G = 0) gives every wave its own G, so one launch can run the longest chains on
+// whole waves and the shortest four to a wave.  Bead j of a walker lives in lane (j mod G) of its
+// group, slot j / G.  Values that are uniform within a group (bead index, energy, bin, ...) are
+// plain VGPRs.  The coordinates live in LDS only: each group reads "its" moved bead, the
+// neighbours and its lanes' own beads there with ordinary LDS loads, and an accepted move is
+// written by all lanes of its group.
 // ln W (Eq. 8) is continuous and linear inside each bin, so LDS holds its values at the K + 1 bin
 // edges (8 bytes per bin) and a move reads the two edges of its bin with one ds_read2; the
 // runtime uses this kernel only for weights that are continuous (the Berg recursion keeps them
