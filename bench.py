@@ -476,18 +476,28 @@ def copy_calibration(n_mib: int = 512, reps: int = 3):
     return n_mib
 
 
+def code_hash(files) -> str:
+    """SHA-256 of the given sources with comments and whitespace removed, so that editing a
+    comment does not void a measurement of the code."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for f in files:
+        txt = open(os.path.join(ROOT, f)).read()
+        txt = re.sub(r"/\*.*?\*/", " ", txt, flags=re.S)
+        txt = re.sub(r"//[^\n]*", " ", txt)
+        h.update(re.sub(r"\s+", " ", txt).strip().encode())
+    return h.hexdigest()
+
+
 def sweep_counters():
     """The committed rocprofv3 counter record of the sweep launch (HBM bytes, VALU instructions
-    per launch), or None when the sweep kernel sources changed since the counters were taken."""
-    import hashlib
+    per launch), or None when the sweep kernel's code changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "sweep_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    h = hashlib.sha256()
-    for f in rec.get("sources", []):
-        h.update(open(os.path.join(ROOT, f), "rb").read())
-    if h.hexdigest() != rec.get("sources_sha256"):
+    if code_hash(rec.get("sources", [])) != rec.get("sources_code_sha256"):
         return None
     return rec
 
