@@ -1,8 +1,9 @@
 """Parity at the benchmark's full sizes and launch configurations, on sampled outputs the oracle
-computes one by one: the batched workload (32 systems, 4096 walkers, two walkers per wave in
-paired workgroups) in FP64 mode against oracle walkers of the same index, the same workload in
-the benchmarked FP32-split mode against the FP64 energy of each sampled walker's coordinates,
-and the energy kernels on 10^6 configurations."""
+computes one by one: the batched workload (32 systems, 4096 walkers; two walkers per wave in
+paired workgroups, the mixed plan, and the plan the autotuner picks for the benchmark) in FP64
+mode against oracle walkers of the same index, the same workload in the benchmarked FP32-split
+mode against the FP64 energy of each sampled walker's coordinates, and the energy kernels on
+10^6 configurations."""
 import numpy as np
 import pytest
 
@@ -21,13 +22,25 @@ def lib():
     return P
 
 
-def test_batched_full_size_fp64_sampled_walkers(lib, orc):
+@pytest.mark.parametrize("plan", ["two_per_wave", "mixed", "autotuned"])
+def test_batched_full_size_fp64_sampled_walkers(lib, orc, plan):
+    """FP64 trajectories of sampled walkers in the two-walkers-per-wave plan, the mixed plan
+    with every qualifying system on whole waves, and whatever plan the autotuner picks (the
+    benchmark's)."""
     wl = workloads.batched_chains()
     n_sweeps = 12
-    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), precision=0,
-                               walkers_per_wave=2, waves_per_block=8)
+    kw = dict(walkers_per_wave=2, waves_per_block=8) if plan == "two_per_wave" else (
+        dict(walkers_per_wave=-1) if plan == "mixed" else {})
+    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), precision=0, **kw)
+    if plan == "autotuned":
+        m.autotune(probe_sweeps=20)
     info = m.launch_info()
-    assert info["walkers_per_wave"] == 2 and info["paired"] == 1 and info["workgroups"] == 256
+    print("launch plan", info)
+    assert info["workgroups"] <= 256
+    if plan == "two_per_wave":
+        assert info["walkers_per_wave"] == 2 and info["paired"] == 1 and info["workgroups"] == 256
+    if plan == "mixed":
+        assert info["walkers_per_wave"] == -1 and info["lanes_used"] == 0b111
     n_log = n_sweeps * min(sp.n_beads for sp in wl.systems)
     m.set_accept_log(n_log)
     m.sweep(n_sweeps)
@@ -51,15 +64,20 @@ def test_batched_full_size_fp64_sampled_walkers(lib, orc):
     m.close()
 
 
-def test_batched_full_size_fp32_split_energies(lib, orc):
+@pytest.mark.parametrize("plan", ["two_per_wave", "autotuned"])
+def test_batched_full_size_fp32_split_energies(lib, orc, plan):
     """The benchmarked mode (FP32 pair terms, FP64 resync every 100 sweeps) after two MUCA
-    iterations: every sampled walker's running energy is the FP64 energy of its coordinates
-    within 1e-5 of the sum of term magnitudes, its bonds are unit, and every trial move was
-    counted once in its system's histogram."""
+    iterations, in the two-walkers plan and in the autotuned plan the benchmark runs: every
+    sampled walker's running energy is the FP64 energy of its coordinates within 1e-5 of the sum
+    of term magnitudes, its bonds are unit, and every trial move was counted once in its
+    system's histogram."""
     wl = workloads.batched_chains()
     n_sweeps = 250
-    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers_per_wave=2,
-                               waves_per_block=8)
+    kw = dict(walkers_per_wave=2, waves_per_block=8) if plan == "two_per_wave" else {}
+    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), **kw)
+    if plan == "autotuned":
+        m.autotune(probe_sweeps=500)
+        print("launch plan", m.launch_info())
     m.iterate(n_sweeps, 2)
     st = m.stats_history(0, 2)
     for s in SAMPLED_SYSTEMS:
