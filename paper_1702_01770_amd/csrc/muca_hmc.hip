@@ -237,14 +237,14 @@ __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs 
                     vx += hs * mx; vy += hs * my; vz += hs * mz;
                 } else {
                     const double sp = sqrt(mx * mx + my * my + mz * mz);
-                    const double c = cos(sp * hs), s = sin(sp * hs);
-                    const double safe = sp > 0.0 ? sp : 1.0;
-                    double ux = vx * c + (mx / safe) * s, uy = vy * c + (my / safe) * s,
-                           uz = vz * c + (mz / safe) * s;
+                    double s, c;
+                    sincos(sp * hs, &s, &c);
+                    const double is = s / (sp > 0.0 ? sp : 1.0);     // sin(|w| h) / |w|
+                    double ux = vx * c + mx * is, uy = vy * c + my * is, uz = vz * c + mz * is;
                     double wx = mx * c - vx * (sp * s), wy = my * c - vy * (sp * s),
                            wz = mz * c - vz * (sp * s);
-                    const double nu = sqrt(ux * ux + uy * uy + uz * uz);
-                    ux /= nu; uy /= nu; uz /= nu;
+                    const double inu = 1.0 / sqrt(ux * ux + uy * uy + uz * uz);
+                    ux *= inu; uy *= inu; uz *= inu;
                     const double d = wx * ux + wy * uy + wz * uz;
                     wx -= d * ux; wy -= d * uy; wz -= d * uz;
                     vx = ux; vy = uy; vz = uz; mx = wx; my = wy; mz = wz;
