@@ -195,7 +195,7 @@ PAPER_SWEEPS_PER_ITERATION = {"abeta_dimer": 10 ** 6, "cross_human": 10 ** 7, "c
 
 
 def paper_physics_leg(stream, names, iters=1000, walkers=4096, first=700, block=25,
-                      hmc_traj=0, hmc_steps=10, hmc_step=0.01, reset_every=0):
+                      hmc_traj=0, hmc_steps=10, hmc_step=0.01, reset_every=0, e_hi=None):
     """Full multicanonical runs of the paper's example systems as in Sec. 4: `walkers` walkers
     share the paper's sweeps per iteration, `iters` Berg iterations, then the
     microcanonical analysis (Eqs. 4-8) of iterations [first, iters) in blocks of `block`:
@@ -206,12 +206,12 @@ def paper_physics_leg(stream, names, iters=1000, walkers=4096, first=700, block=
     (hmc_steps leapfrog steps of hmc_step) before the weight update.  With reset_every > 0 the
     recursion's accumulated statistics g are cleared every reset_every iterations before the
     analysed range, so estimates from the early, far-from-equilibrium iterations stop weighing
-    on the weights."""
+    on the weights.  e_hi (total energy) moves the window's upper edge from +N."""
     import paper_1702_01770_amd as P
     import workloads
     out = {}
     for name in names:
-        wl = workloads.paper_system(name, walkers=walkers)
+        wl = workloads.paper_system(name, walkers=walkers, e_hi=e_hi)
         sp = wl.systems[0]
         sweeps = -(-PAPER_SWEEPS_PER_ITERATION[name] // walkers)
         m = P.Muca.from_workload(wl, workloads.initial_positions(wl),
@@ -253,6 +253,7 @@ def paper_physics_leg(stream, names, iters=1000, walkers=4096, first=700, block=
                                        n_monomers=sp.n_beads)
         dbeta = np.diff(res["beta"])
         rec = {"beads": sp.n_beads, "sphere_radius": wl.box_len, "iterations": iters,
+               "window": [sp.e_lo, sp.e_lo + sp.n_bins * wl.bin_width],
                "sweeps_per_iteration": sweeps * wl.walkers_per_system,
                "walkers": walkers, "hmc_trajectories_per_iteration": hmc_traj,
                "recursion_reset_every": reset_every,
@@ -528,6 +529,8 @@ def main():
                     help="comma-separated paper systems: only run their full MUCA + analysis")
     ap.add_argument("--physics-iters", type=int, default=1000)
     ap.add_argument("--physics-walkers", type=int, default=4096)
+    ap.add_argument("--physics-ehi", type=float, default=None,
+                    help="upper edge of the energy window (total energy) in the physics leg")
     ap.add_argument("--physics-reset", type=int, default=0,
                     help="clear the recursion's accumulated statistics every N iterations")
     ap.add_argument("--physics-hmc", type=int, default=0,
@@ -553,7 +556,7 @@ def main():
         print(json.dumps({"paper_physics": paper_physics_leg(
             st, args.paper_physics.split(","), iters=args.physics_iters,
             walkers=args.physics_walkers, hmc_traj=args.physics_hmc,
-            reset_every=args.physics_reset,
+            reset_every=args.physics_reset, e_hi=args.physics_ehi,
             first=int(0.7 * args.physics_iters), block=max(1, args.physics_iters // 40))}))
         return
     if args.diff_only:

@@ -21,7 +21,7 @@ is reproducible bit for bit.
 from __future__ import annotations
 
 from dataclasses import dataclass, field
-from typing import List
+from typing import List, Optional
 
 import numpy as np
 
@@ -236,16 +236,19 @@ def ab_from_string(seq: str) -> np.ndarray:
 def paper_system(name: str = "cross_human", walkers: int = 4096,
                  precision: int = PREC_FP32_SPLIT, pivot_per_sweep: int = 1,
                  rotate_per_sweep: int = 1, bin_width: float = 0.05, seed: int = 1702,
-                 beta_max: float = 6.0, n_iter: int = 10, n_sweeps: int = 10000) -> Workload:
+                 beta_max: float = 6.0, n_iter: int = 10, n_sweeps: int = 10000,
+                 e_hi: Optional[float] = None) -> Workload:
     """One of PAPER_SYSTEMS in its steric sphere with the paper's move set: single-bead moves,
     rigid translations, pivots and rigid chain rotations (the last two per sweep as given).
     The weight recursion is bounded to inverse temperatures [0, beta_max]: the steep slopes that
     sparse first-iteration tails produce would otherwise be copied to every lower bin and
-    freeze the walkers there."""
+    freeze the walkers there.  e_hi (total energy) moves the window's upper edge from +N."""
     seqs, radius = PAPER_SYSTEMS[name]
     types = np.concatenate([ab_from_string(q) for q in seqs])
     lens = [len(q) for q in seqs]
     e_lo, n_bins = default_window(sum(lens), bin_width)
+    if e_hi is not None:
+        n_bins = int(round((e_hi - e_lo) / bin_width))
     sys_ = SystemSpec(chain_len=lens, types=types, e_lo=e_lo, n_bins=n_bins)
     return Workload(name=f"paper_{name}_R{radius:g}", systems=[sys_], walkers_per_system=walkers,
                     box_kind=BOX_SPHERE, box_len=radius, bin_width=bin_width,
