@@ -557,8 +557,42 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                             qx[s] * qx[s] + qy[s] * qy[s] + qz[s] * qz[s] > a.sphere_r2)
                             outside += (A)1;
                     }
-                    // pair terms between the moved beads (this lane's) and every bead that stays
+                    // pair terms between the moved and the fixed beads, looping over the smaller
+                    // set: over the moved beads (their new position computed by every lane) with
+                    // the lanes holding the fixed ones, or over the fixed beads with the lanes
+                    // holding the moved ones
                     A pacc = 0;
+                    if (2 * (hi - lo + 1) <= N) {
+                        for (int ib = lo; ib <= hi; ++ib) {
+                            const double xi = L.x[ib], yi = L.y[ib], zi = L.z[ib];
+                            double vx = xi - ox, vy = yi - oy, vz = zi - oz;
+                            rot3(kx, ky, kz, co, sn, vx, vy, vz);
+                            const double xn = ox + vx, yn = oy + vy, zn = oz + vz;
+                            const int infi = L.binfo[ib];
+                            const int ci = bi_chain(infi), ti = bi_type(infi);
+#pragma unroll
+                            for (int s = 0; s < SLOTS; ++s) {
+                                const int j = gl + G * s;
+                                const bool same = chn[s] == ci;
+                                if (j < N && !(j >= lo && j <= hi) &&
+                                    !(same && (j == ib + 1 || j + 1 == ib))) {
+                                    double dxo = px[s] - xi, dyo = py[s] - yi, dzo = pz[s] - zi;
+                                    double dxn = px[s] - xn, dyn = py[s] - yn, dzn = pz[s] - zn;
+                                    if constexpr (PERIODIC) {
+                                        dxo = min_img(dxo, a.box_len, a.inv_box);
+                                        dyo = min_img(dyo, a.box_len, a.inv_box);
+                                        dzo = min_img(dzo, a.box_len, a.inv_box);
+                                        dxn = min_img(dxn, a.box_len, a.inv_box);
+                                        dyn = min_img(dyn, a.box_len, a.inv_box);
+                                        dzn = min_img(dzn, a.box_len, a.inv_box);
+                                    }
+                                    const double kk = same ? a.k_intra : a.k_inter;
+                                    pacc += pair_d<FP64>(dxo, dyo, dzo, dxn, dyn, dzn, kk,
+                                                         kk * L.ctab[trow[s] + ti]);
+                                }
+                            }
+                        }
+                    } else
                     for (int jb = 0; jb < N; ++jb) {
                         if (jb >= lo && jb <= hi) continue;          // uniform: both moved
                         const double xj = L.x[jb], yj = L.y[jb], zj = L.z[jb];
