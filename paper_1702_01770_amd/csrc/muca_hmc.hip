@@ -27,20 +27,39 @@ struct HmcLds {
     double bp[64][3], bq[64][3], tp[64][3], tq[64][3];
 };
 
+// v from the lane that DPP control CTRL selects, 0 where that lane is outside the row or the
+// row is not in ROWS (the two 32-bit halves moved separately).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_from(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, ROWS, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, ROWS, 0xf, true);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Inclusive prefix sum within the segment [cs, ...] of each lane (segments are contiguous lane
+// ranges).  Kogge-Stone inside each 16-lane row (row shifts by 1, 2, 4, 8), then the last lane
+// of row 0 / 2 added to rows 1 / 3 and lane 31 to rows 2 and 3; every step adds only what comes
+// from the lane's own segment.  No LDS round trips.
 __device__ __forceinline__ double seg_prefix(double v, int lane, int cs) {
-    for (int d = 1; d < 64; d <<= 1) {
-        const double y = __shfl_up(v, d);
-        if (lane - d >= cs) v += y;
-    }
+    const int r = lane & 15;
+    double t;
+    t = dpp_from<0x111, 0xf>(v); if (r >= 1 && lane - 1 >= cs) v += t;
+    t = dpp_from<0x112, 0xf>(v); if (r >= 2 && lane - 2 >= cs) v += t;
+    t = dpp_from<0x114, 0xf>(v); if (r >= 4 && lane - 4 >= cs) v += t;
+    t = dpp_from<0x118, 0xf>(v); if (r >= 8 && lane - 8 >= cs) v += t;
+    t = dpp_from<0x142, 0xa>(v);                    // row_bcast:15 into rows 1 and 3
+    if ((lane & 16) && (lane & ~15) - 1 >= cs) v += t;
+    t = dpp_from<0x143, 0xc>(v);                    // row_bcast:31 into rows 2 and 3
+    if (lane >= 32 && 31 >= cs) v += t;
     return v;
 }
 
-__device__ __forceinline__ double seg_suffix(double v, int lane, int ce) {
-    for (int d = 1; d < 64; d <<= 1) {
-        const double y = __shfl_down(v, d);
-        if (lane + d <= ce) v += y;
-    }
-    return v;
+// Inclusive suffix sum within the segment [..., ce]: the segment's total (the prefix at ce) minus
+// the prefix before this lane.
+__device__ __forceinline__ double seg_suffix(double v, int lane, int cs, int ce) {
+    const double p = seg_prefix(v, lane, cs);
+    return (__shfl(p, ce) - p) + v;
 }
 
 // 1 / x for a positive normal x: the hardware estimate refined by two Newton steps
@@ -215,9 +234,9 @@ __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs 
         double Ec = energy_forces<PERIODIC>(a, L, bi, ct, N, lane, ce, gx, gy, gz);
         auto gen_forces = [&](double Ecur, double &Gx, double &Gy, double &Gz) {
             const double b = beta[bin_of(Ecur, e_lo, eps, K)];
-            Gx = seg_suffix(-b * gx, lane, ce);
-            Gy = seg_suffix(-b * gy, lane, ce);
-            Gz = seg_suffix(-b * gz, lane, ce);
+            Gx = seg_suffix(-b * gx, lane, cs, ce);
+            Gy = seg_suffix(-b * gy, lane, cs, ce);
+            Gz = seg_suffix(-b * gz, lane, cs, ce);
         };
         double Gx, Gy, Gz;
         gen_forces(Ec, Gx, Gy, Gz);
