@@ -25,9 +25,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (published, packed)
-# wave64 VALU instructions the chip can issue per second: 256 CUs x 4 SIMDs, one instruction
-# every 4 cycles per SIMD (64 lanes on 16-wide units) at 2.4 GHz
-PEAK_VALU_INSTS = 256 * 4 * 2.4e9 / 4
 
 
 def algorithmic_flops_per_move(n_beads: int, n_chains: int = 1, periodic: bool = False,
@@ -591,14 +588,6 @@ def main():
         "acceptance": r["acc_rate"],
         "wall_s": r["wall_s"],
     }
-    rec = sweep_counters()
-    if rec and rec.get("valu_insts_per_launch"):
-        # issue-rate view of the same launches: profiled wave instructions per launch over the
-        # launch time measured here
-        rate = rec["valu_insts_per_launch"] / (out["sweep_launch"]["avg_ms"] / 1e3)
-        out["valu_issue"] = {"insts_per_launch": rec["valu_insts_per_launch"],
-                             "achieved_per_s": rate, "peak_per_s": PEAK_VALU_INSTS,
-                             "frac": rate / PEAK_VALU_INSTS}
     if not args.no_plain:
         rp = run_gpu(wl, 1, args.plain_sweeps, 1, 0, st, autotune=False)
         plain = rp["moves"] / (rp["event_ms"] / 1e3)
