@@ -349,6 +349,39 @@ def test_checkpoint_resume_is_bit_identical(lib):
     c.close()
 
 
+def test_fp64_resume_across_launch_plans(lib):
+    """FP64 trajectories do not depend on the launch plan: a run in the mixed plan (16-, 32- and
+    64-lane walkers) saved after a weight update and resumed with two walkers per wave ends in
+    exactly the state of an uninterrupted run in one walker per wave."""
+    wl = workloads.chains_of_lengths([12, 24, 40, 56])
+    p0 = workloads.initial_positions(wl)
+    a = lib.Muca.from_workload(wl, p0, walkers=4, precision=0, walkers_per_wave=1)
+    a.sweep(120)
+    a.update_weights()
+    a.sweep(80)
+    b = lib.Muca.from_workload(wl, p0, walkers=4, precision=0, walkers_per_wave=-1)
+    assert b.launch_info()["lanes_used"] == 0b111
+    b.sweep(120)
+    b.update_weights()
+    blob = b.get_state()
+    b.close()
+    c = lib.Muca.from_workload(wl, p0, walkers=4, precision=0, walkers_per_wave=2)
+    c.set_state(blob)
+    c.sweep(80)
+    for s in range(wl.n_systems):
+        pa, ea, ca = a.walkers_state(s)
+        pc, ec, cc = c.walkers_state(s)
+        assert np.allclose(pa, pc, rtol=0, atol=1e-10)
+        assert np.allclose(ea, ec, rtol=0, atol=1e-9)
+        assert np.array_equal(a.histogram(s), c.histogram(s))
+        for k in ("moves", "accepted", "window_rejects", "sweeps"):
+            assert np.array_equal(ca[k], cc[k])
+        for x, y in zip(a.weights(s), c.weights(s)):
+            assert np.allclose(x, y, rtol=0, atol=1e-12)
+    a.close()
+    c.close()
+
+
 def test_drift_detector_fires_on_corrupted_energy(lib):
     """The FP64 resync compares the running energy with a full recomputation and reports
     MUCA_E_DRIFT when they differ by more than drift_tol (here a corrupted running energy)."""
