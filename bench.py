@@ -541,7 +541,7 @@ def main():
     ap.add_argument("--waves-per-block", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark measures one GPU (no multi-GPU path is implemented); --gpus must be 1"}))
         sys.exit(2)
     import workloads
 

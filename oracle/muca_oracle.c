@@ -27,8 +27,8 @@
 /* ------------------------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3",  */
 /* SC'11).  Counter-based: out = f_key(counter).  The paper's package draws uniforms from     */
-/* cuRAND vectors (Sec. 3.2, RANDOM.f / cudaRandom.cu); this build replaces them by one       */
-/* Philox block per trial move so that CPU and GPU can draw identical streams.                */
+/* cuRAND vectors (Sec. 3.2, RANDOM.f / cudaRandom.cu); this implementation draws one Philox   */
+/* block per trial move instead, so that CPU and GPU can draw identical streams.              */
 /* ------------------------------------------------------------------------------------------ */
 static const uint32_t PHILOX_M0 = 0xD2511F53u, PHILOX_M1 = 0xCD9E8D57u;
 static const uint32_t PHILOX_W0 = 0x9E3779B9u, PHILOX_W1 = 0xBB67AE85u;
@@ -226,7 +226,7 @@ static double inter_terms_of_chain(const orc_system *s, const double *pos, int c
 }
 
 /* ------------------------------------------------------------------------------------------ */
-/* Trial moves (paper: spherical caps, pivots, Galilean updates, Sec. 3.2).  This build moves  */
+/* Trial moves (paper: spherical caps, pivots, Galilean updates, Sec. 3.2).  This code moves   */
 /* one bead at a time and keeps every bond at r0 = 1 (AB limit, kappa_F = 0), so Delta E is    */
 /* O(N).  Both proposals are symmetric, hence plain Metropolis acceptance is exact.            */
 /* ------------------------------------------------------------------------------------------ */
