@@ -186,7 +186,8 @@ __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs 
         ct[threadIdx.x] = make_double2(kap, kap * c);
     }
     __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index is uniform: everything per walker derived from it stays in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int w = blockIdx.x * kHmcWaves + wave;
     if (w >= h.n_walkers) return;                 // no workgroup barrier below this one
     HmcLds &L = lds[wave];
@@ -203,7 +204,6 @@ __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs 
     const double e_lo = sd.e_lo, eps = a.bin_width;
     const double *beta = a.beta + sd.bin_off, *alpha = a.alpha + sd.bin_off;
     double *P = a.pos + (size_t)w * 3 * a.npad;
-    double x = act ? P[lane] : 0.0, y = act ? P[a.npad + lane] : 0.0, z = act ? P[2 * a.npad + lane] : 0.0;
     double E = a.energy[w];
     unsigned long long *hc = h.cnt + (size_t)w * 2;
     unsigned long long T = hc[0];
@@ -212,6 +212,10 @@ __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs 
     const double hs = h.step;
 
     for (long long tr = 0; tr < h.n_traj; ++tr, ++T) {
+        // the walker's state stays in its position rows (rewritten on acceptance), read once per
+        // trajectory, so that no register holds it across the force evaluations
+        const double x = act ? P[lane] : 0.0, y = act ? P[a.npad + lane] : 0.0,
+                     z = act ? P[2 * a.npad + lane] : 0.0;
         L.x[lane] = x; L.y[lane] = y; L.z[lane] = z;
         __builtin_amdgcn_wave_barrier();
         // vectors: the first bead's position, else the bond ending at this bead
@@ -248,7 +252,6 @@ __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs 
             }
             if (act) { mx += hh * tx; my += hh * ty; mz += hh * tz; }
         };
-        double nx = x, ny = y, nz = z;
         for (int st = 0; st < h.n_steps; ++st) {
             kick(0.5 * hs);
             if (act) {
@@ -269,15 +272,16 @@ __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs 
                     vx = ux; vy = uy; vz = uz; mx = wx; my = wy; mz = wz;
                 }
             }
-            nx = seg_prefix(vx, lane, cs);
-            ny = seg_prefix(vy, lane, cs);
-            nz = seg_prefix(vz, lane, cs);
-            L.x[lane] = nx; L.y[lane] = ny; L.z[lane] = nz;
+            L.x[lane] = seg_prefix(vx, lane, cs);
+            L.y[lane] = seg_prefix(vy, lane, cs);
+            L.z[lane] = seg_prefix(vz, lane, cs);
             __builtin_amdgcn_wave_barrier();
             Ec = energy_forces<PERIODIC>(a, L, bi, ct, N, lane, ce, gx, gy, gz);
             gen_forces(Ec, Gx, Gy, Gz);
             kick(0.5 * hs);
         }
+        // positions at the end of the trajectory (n_steps >= 1: the last drift wrote them)
+        const double nx = L.x[lane], ny = L.y[lane], nz = L.z[lane];
         const double t1 = (Ec - e_lo) / eps;
         const bool inwin = t1 >= 0.0 && t1 < (double)K;
         const bool out = act && a.sphere_r2 > 0.0 && nx * nx + ny * ny + nz * nz > a.sphere_r2;
@@ -289,7 +293,7 @@ __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs 
         const bool accept = inwin && inside && (log(u01(ra.x)) < H0 - H1);
         n_wrej += inwin ? 0 : 1;
         if (accept) {
-            x = nx; y = ny; z = nz;
+            if (act) { P[lane] = nx; P[a.npad + lane] = ny; P[2 * a.npad + lane] = nz; }
             E = Ec;
             ++n_acc;
         }
@@ -298,7 +302,6 @@ __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs 
         }
         __builtin_amdgcn_wave_barrier();   // L.x is rewritten by the next trajectory
     }
-    if (act) { P[lane] = x; P[a.npad + lane] = y; P[2 * a.npad + lane] = z; }
     if (lane == 0) {
         a.energy[w] = E;
         hc[0] = T;
