@@ -98,16 +98,23 @@ __device__ double energy_forces(const SweepArgs &a, HmcLds &L, const int *bi, co
     __builtin_amdgcn_wave_barrier();
     const int infj = bi[lane], tj = bi_type(infj), cj = bi_chain(infj);
     const int dmax = N / 2;
+    // partner of offset d: i = lane + d mod N (always inside the 64-entry arrays); its bead info
+    // and coordinates are requested one offset ahead, before the arithmetic of the current one
+    int i = lane + 1;
+    if (i >= N) i -= N;
+    int infi = bi[i];
+    double xi = L.x[i], yi = L.y[i], zi = L.z[i];
     for (int d = 1; d <= dmax; ++d) {
-        int i = lane + d;
-        if (i >= N) i -= N;
-        const int infi = bi[i];
+        int i2 = i + 1;
+        if (i2 >= N) i2 -= N;
+        const int infi2 = bi[i2];
+        const double xi2 = L.x[i2], yi2 = L.y[i2], zi2 = L.z[i2];
         const bool same = bi_chain(infi) == cj;
         // bonded neighbours (i = j + 1 in one chain), lanes past the beads, and the second copy
         // of each pair at d = N/2 when N is even
         const bool use = act && !(same && d == 1 && i == lane + 1) &&
                          !(2 * d == N && lane >= dmax);
-        double dx = xj - L.x[i], dy = yj - L.y[i], dz = zj - L.z[i];
+        double dx = xj - xi, dy = yj - yi, dz = zj - zi;
         if constexpr (PERIODIC) {
             dx -= a.box_len * rint(dx * a.inv_box);
             dy -= a.box_len * rint(dy * a.inv_box);
@@ -125,6 +132,7 @@ __device__ double energy_forces(const SweepArgs &a, HmcLds &L, const int *bi, co
         atomicAdd(&L.rx[i], -fx);
         atomicAdd(&L.ry[i], -fy);
         atomicAdd(&L.rz[i], -fz);
+        i = i2; infi = infi2; xi = xi2; yi = yi2; zi = zi2;
     }
     __builtin_amdgcn_wave_barrier();
     gx += L.rx[lane]; gy += L.ry[lane]; gz += L.rz[lane];
