@@ -29,6 +29,9 @@ def _canonical(sp, wl, T):
     (lambda: workloads.aggregation(walkers=4), 0.8, 6, 0.04),
     (lambda: workloads.confined(radius=6.0, walkers=4), 0.8, 6, 0.05),
     (lambda: workloads.paper_system("abeta_dimer", walkers=4), 0.7, 6, 0.05),
+    # the largest chain one wave holds: every lane a bead, partners wrap at lane 63, and the
+    # pairs at offset N/2 = 32 are taken by the lower half of the lanes only
+    (lambda: workloads.single_chain(n=64), 0.6, 8, 0.03),
 ])
 def test_hmc_matches_oracle(lib, orc, make, T, steps, h):
     wl = make()
