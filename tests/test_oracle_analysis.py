@@ -101,3 +101,93 @@ def test_block_errors_from_scattered_iterations():
     blocks = np.array(blocks)
     assert np.allclose(r["beta"], blocks.mean(axis=0), atol=1e-12)
     assert np.allclose(r["dbeta"], blocks.std(axis=0, ddof=1) / 2.0, atol=1e-12)
+
+
+def _sbend_blocks(b0s, As, b, e_lo, eps, K):
+    """One iteration per block; block i has the caloric curve beta = b0_i + a_i x - b x^3."""
+    rows_b, rows_a = [], []
+    for b0, a in zip(b0s, As):
+        S = lambda e, b0=b0, a=a: b0 * e + a * e * e / 2 - b * e ** 4 / 4
+        bb, aa = A.coefficients_from_entropy(S, e_lo, eps, K)
+        rows_b.append(bb)
+        rows_a.append(aa)
+    return np.array(rows_b), np.array(rows_a)
+
+
+@pytest.mark.parametrize("N", [1, 6])
+def test_maxwell_jackknife_errors_have_closed_forms(N):
+    """Leave-one-block-out jackknife of the Maxwell construction (Sec. 3.3; binning over
+    iterations, Sec. 4.1).  Block i carries the S-bend beta_i(E) = b0_i + a_i x - b x^3, so every
+    leave-one-out average is again such an S-bend with the mean parameters of the other blocks,
+    whose Maxwell line, latent heat and barrier are known exactly: beta_c = b0, latent heat
+    2 sqrt(a/b), barrier a^2 / (4 b b0).  For beta_c the jackknife error then equals the standard
+    error of the mean of the b0_i (a property of the jackknife for a linear statistic), which
+    pins the (nb - 1)/nb factor and the centring independently of the code's own formula."""
+    b0s = np.array([0.80, 0.83, 0.78, 0.81, 0.795, 0.82])
+    As = np.array([0.30, 0.33, 0.28, 0.31, 0.295, 0.32])
+    b = 0.12
+    nb = len(b0s)
+    eps, K = 0.004, 2400
+    e_lo = -K * eps / 2
+    B, Al = _sbend_blocks(b0s, As, b, e_lo, eps, K)
+    r = A.analyze(B, Al, e_lo, eps, 0, K, 0, nb, 1, eps, beta_c=0.0, tol_beta=1e-3, tol_l=0.0,
+                  n_monomers=N)
+    m_b0, m_a = b0s.mean(), As.mean()
+    assert r["beta_c"] == pytest.approx(m_b0, abs=1e-6)
+    assert r["latent"] == pytest.approx(2 * math.sqrt(m_a / b) / N, rel=1e-4)
+    assert r["barrier"] == pytest.approx(m_a ** 2 / (4 * b * m_b0) / N, rel=1e-3)
+    # beta_c: jackknife of a mean is the standard error of the mean
+    se_b0 = b0s.std(ddof=1) / math.sqrt(nb)
+    assert r["dbeta_c"] == pytest.approx(se_b0, rel=1e-3)
+    # latent heat and barrier: jackknife over the closed-form leave-one-out values
+    loo_b0 = (b0s.sum() - b0s) / (nb - 1)
+    loo_a = (As.sum() - As) / (nb - 1)
+    lat = 2 * np.sqrt(loo_a / b) / N
+    bar = loo_a ** 2 / (4 * b * loo_b0) / N
+
+    def jk(v):
+        return math.sqrt((nb - 1) / nb * np.sum((v - v.mean()) ** 2))
+
+    assert r["dlatent"] == pytest.approx(jk(lat), rel=2e-3)
+    assert r["dbarrier"] == pytest.approx(jk(bar), rel=2e-2)
+    # delta method, to first order in the spread of a: d latent = std(a) / sqrt(nb a b) / N
+    assert r["dlatent"] == pytest.approx(As.std(ddof=1) / math.sqrt(nb * m_a * b) / N, rel=0.05)
+
+
+def test_maxwell_jackknife_vanishes_for_identical_blocks():
+    B, Al = _sbend_blocks([0.8] * 4, [0.3] * 4, 0.12, -4.0, 0.004, 2000)
+    r = A.analyze(B, Al, -4.0, 0.004, 0, 2000, 0, 4, 1, 0.004, beta_c=0.0, tol_beta=1e-3)
+    assert r["dbeta_c"] < 1e-9 and r["dlatent"] < 1e-7 and r["dbarrier"] < 1e-7
+
+
+@pytest.mark.parametrize("maxwell", [False, True])
+def test_free_energy_errors_from_tilted_blocks(maxwell):
+    """F(E) = E - S(E)/beta_c (Eq. 7) per block; the error is the standard error over blocks
+    (Sec. 4.1).  Blocks whose entropies differ by a tilt c_i (E - E_ref) have, after the
+    normalisation S(E_ref) = 0, F errors std(c) |E - E_ref| / (N beta_c sqrt(nb)) in intensive
+    units: zero at the reference point and growing linearly away from it."""
+    cs = np.array([0.0, 0.02, -0.01, 0.015, -0.025])
+    nb, N = len(cs), 4
+    eps, K = 0.004, 2000
+    e_lo = -K * eps / 2
+    b0, a, b = 0.8, 0.3, 0.12
+    rows_b, rows_a = [], []
+    for c in cs:
+        S = lambda e, c=c: (b0 + c) * e + a * e * e / 2 - b * e ** 4 / 4
+        bb, aa = A.coefficients_from_entropy(S, e_lo, eps, K)
+        rows_b.append(bb)
+        rows_a.append(aa)
+    B, Al = np.array(rows_b), np.array(rows_a)
+    kw = dict(beta_c=0.0, tol_beta=1e-3) if maxwell else dict(beta_c=1.7)
+    r = A.analyze(B, Al, e_lo, eps, 0, K, 0, nb, 1, eps, n_monomers=N, **kw)
+    bc = r["beta_c"]
+    if maxwell:
+        assert bc == pytest.approx(b0 + cs.mean(), abs=1e-6)
+    else:
+        assert bc == 1.7
+    e_ref = r["E"][-1] * N
+    expect = cs.std(ddof=1) * np.abs(r["E"] * N - e_ref) / (N * bc * math.sqrt(nb))
+    assert np.allclose(r["dF"], expect, rtol=1e-9, atol=1e-12)
+    # and the mean F is that of the mean entropy
+    s_mean = r["S"]
+    assert np.allclose(r["F"], r["E"] - s_mean / bc, atol=1e-12)
