@@ -178,8 +178,9 @@ int muca_update_weights(muca_ctx *ctx, muca_iter_stats *stats);
  * -beta(E) dE/dx of U = -ln W(E) (Eq. 8, beta the slope of -ln W in the bin of E).  Momenta:
  * Box-Muller normals from Philox blocks (bead j, lo32(T), hi32(T), 7) of the walker's key, T
  * the walker's trajectory count; acceptance: ln u < H_old - H_new with u from block
- * (0, lo32(T), hi32(T), 8), H = -ln W(E) + |p|^2 / 2; an end outside the window or the
- * sphere rejects.  One histogram count per trajectory at the energy after the decision (added
+ * (0, lo32(T), hi32(T), 8), H = -ln W(E) + |p|^2 / 2 with the starting E recomputed in FP64
+ * from the coordinates (not the running energy of the sweeps); an end outside the window or the
+ * sphere rejects, and a rejected trajectory leaves the walker with that recomputed energy.  One histogram count per trajectory at the energy after the decision (added
  * to the running histogram the weight update reads).  Energies and forces in FP64 in both
  * precision modes.  At most 64 beads per system (MUCA_E_INVAL otherwise); n_steps >= 1,
  * step > 0. */
@@ -215,9 +216,13 @@ int muca_get_walkers(muca_ctx *ctx, int32_t sys, double *pos, double *energy,
  * device and must lie in the window (MUCA_E_WINDOW). */
 int muca_set_walkers(muca_ctx *ctx, int32_t sys, const double *pos, const uint64_t *sweeps);
 
-/* Record the accept/reject decision of the first n_moves single-bead trial moves of every
- * walker in each following muca_sweep call (0 disables).  The log of system sys is read as
- * host bytes [walkers][n_moves] (1 = accepted).  Debug aid for trajectory comparisons. */
+/* Record the accept/reject decision of the first n_moves single-bead trial moves every walker
+ * makes after this call, over any number of following muca_sweep calls and launches (0
+ * disables; a new call clears the log and starts counting again).  Moves are counted from the
+ * walker's single-bead move counter at this call; a state restored afterwards with a lower
+ * counter logs only its moves past that point.  The log of system sys is read as host bytes
+ * [walkers][n_moves] (1 = accepted).  Debug aid for trajectory comparisons; muca_iterate
+ * refuses to run while a log is armed. */
 int muca_set_accept_log(muca_ctx *ctx, int64_t n_moves);
 int muca_get_accept_log(muca_ctx *ctx, int32_t sys, uint8_t *out, int64_t n_moves);
 

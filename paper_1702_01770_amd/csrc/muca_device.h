@@ -58,6 +58,8 @@ struct SweepArgs {
     const double *beta, *alpha; // [sum bins]
     unsigned long long *hist;   // [sum bins]
     unsigned int *acc_log;      // [walkers][acc_log_words] or null
+    const unsigned long long *acc_log_base;  // [walkers] single-bead moves done when the log
+                                             // was armed: bit i is the walker's i-th move since
     long long acc_log_moves;
     int acc_log_words;
     int npad;                   // coordinate stride per axis (64 or 128)

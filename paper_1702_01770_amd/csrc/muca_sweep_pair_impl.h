@@ -298,6 +298,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
     long long done = 0;
     int m = 0;
     unsigned int *alog = a.acc_log ? a.acc_log + (size_t)w * a.acc_log_words : nullptr;
+    const long long log0 = alog ? (long long)(cnt[C_MOVES] - a.acc_log_base[w]) : 0;
 
     while (done < total) {
         // ---- each group draws the next (up to) G moves of its walker, one per lane ----
@@ -434,8 +435,10 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 inside = nx * nx + ny * ny + nz * nz <= a.sphere_r2;
             const bool accept = inwin && inside && (q.lnu < lnw_new - lnw_cur);
             n_wrej += inwin ? 0u : 1u;
-            if (alog && (long long)n_mv < a.acc_log_moves && accept && gl == 0)
-                atomicOr(&alog[n_mv >> 5], 1u << (n_mv & 31));
+            if (alog && accept && gl == 0) {
+                const long long li = log0 + n_mv;
+                if (li >= 0 && li < a.acc_log_moves) atomicOr(&alog[li >> 5], 1u << (li & 31));
+            }
             ++n_mv;
             if (accept) {
                 // bonds b-1 and b recomputed from the coordinates (no accumulated rounding)
