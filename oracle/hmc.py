@@ -21,7 +21,9 @@ sample as well:
     then u renormalised and w projected on the tangent plane, positions rebuilt by summing the
     bonds along each chain, forces recomputed, half kick;
   Metropolis on H = U + K: accept iff ln v < H_old - H_new; a final energy outside the window
-    or a bead outside the steric sphere rejects.
+    or a bead outside the steric sphere rejects.  H_old uses the energy recomputed from the
+    starting coordinates, so H is a function of the state; after a rejection the walker keeps
+    that energy.
 
 Random numbers (Philox4x32-10, walker key as for the moves, trajectory counter T):
   momentum of vector j: block (j, lo32(T), hi32(T), 7), uniforms a_i = (x_i + 1/2) 2^-32,
@@ -135,7 +137,10 @@ class HmcWalker:
         T = self.traj
         v = self.vectors(self.pos)
         mom = self.momenta(v, T)
-        e0 = self.energy
+        # H is a function of the state: the start's energy is recomputed from its coordinates
+        # (a running energy handed over by the sweeps need not be the FP64 one); a rejected
+        # trajectory keeps that recomputed energy
+        e0 = self.s.energy(self.pos)
         lnw = lambda e: _lnw(W, e)
         H0 = -lnw(e0) + 0.5 * float(np.sum(mom * mom))
         v, mom, pos = self.leapfrog(v, mom, W, n_steps, h)
@@ -155,6 +160,8 @@ class HmcWalker:
             self.pos = pos
             self.energy = e1
             self.accepted += 1
+        else:
+            self.energy = e0
         if hist is not None:
             k = int((self.energy - W.e_lo) / W.bin_width)
             hist[min(max(k, 0), W.n_bins - 1)] += 1

@@ -239,11 +239,15 @@ __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs 
             mx -= d * vx; my -= d * vy; mz -= d * vz;
         }
         if (!act) { mx = my = mz = 0.0; vx = vy = vz = 0.0; }
-        const double H0 = -(-beta[bin_of(E, e_lo, eps, K)] * E + alpha[bin_of(E, e_lo, eps, K)]) +
-                          0.5 * wave_sum_d(mx * mx + my * my + mz * mz);
-        // forces at the start
+        // forces and FP64 energy at the start.  H0 is built from that energy, not from the
+        // running one, which FP32-split sweeps may have left a little off: H must be a function
+        // of the state for the Metropolis test on it to keep W(E) invariant.
         double gx, gy, gz;
         double Ec = energy_forces<PERIODIC>(a, L, bi, ct, N, lane, ce, gx, gy, gz);
+        const double E0 = Ec;
+        const int kb0 = bin_of(E0, e_lo, eps, K);
+        const double H0 = -(-beta[kb0] * E0 + alpha[kb0]) +
+                          0.5 * wave_sum_d(mx * mx + my * my + mz * mz);
         auto gen_forces = [&](double Ecur, double &Gx, double &Gy, double &Gz) {
             const double b = beta[bin_of(Ecur, e_lo, eps, K)];
             Gx = seg_suffix(-b * gx, lane, cs, ce);
@@ -304,6 +308,8 @@ __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs 
             if (act) { P[lane] = nx; P[a.npad + lane] = ny; P[2 * a.npad + lane] = nz; }
             E = Ec;
             ++n_acc;
+        } else {
+            E = E0;                        // the start's FP64 energy replaces the running one
         }
         if (lane == 0) {
             atomicAdd(&a.hist[sd.bin_off + bin_of(E, e_lo, eps, K)], 1ull);

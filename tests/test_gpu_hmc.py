@@ -79,19 +79,79 @@ def test_hmc_matches_oracle(lib, orc, make, T, steps, h):
 
 
 def test_hmc_then_sweeps_continue_from_the_same_state(lib, orc):
-    """Hybrid MC and single-bead sweeps share the walkers: the running energy after HMC is the
-    FP64 energy of the coordinates, and a following sweep matches the oracle walker continued
-    from those coordinates."""
+    """Hybrid MC and single-bead sweeps share the walkers: after the trajectories the running
+    energy is the FP64 energy of the coordinates, and the following sweeps (coordinates reloaded
+    into LDS, the walker's sweep counter untouched by HMC) match, move for move, an oracle walker
+    continued from the GPU's coordinates with the same walker id and stream position."""
     wl = workloads.single_chain()
     sp = wl.systems[0]
-    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=2, precision=0)
+    n_walk, n_sweeps = 4, 400
+    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=n_walk, precision=0)
     b, a, g = _canonical(sp, wl, 0.7)
     m.set_weights(0, b, a, g)
     m.hmc(10, 6, 0.05)
-    pos_g, e_g, _ = m.walkers_state(0)
+    pos_h, e_h, cnt_h = m.walkers_state(0)
     s = orc.System.from_workload(wl)
-    for i in range(2):
-        assert abs(e_g[i] - s.energy(pos_g[i])) < 1e-10 * max(1.0, s.energy_parts(pos_g[i])[2])
+    for i in range(n_walk):
+        assert abs(e_h[i] - s.energy(pos_h[i])) < 1e-10 * max(1.0, s.energy_parts(pos_h[i])[2])
+    assert np.all(cnt_h["sweeps"] == 0) and np.all(cnt_h["hmc_trajectories"] == 10)
+    assert 0 < cnt_h["hmc_accepted"].sum() < 10 * n_walk
+    H_after_hmc = m.histogram(0).copy()
+    n_log = n_sweeps * sp.n_beads
+    m.set_accept_log(n_log)
+    m.sweep(n_sweeps)
+    log_g = m.accept_log(0)
+    pos_g, e_g, cnt = m.walkers_state(0)
+    H_sweep = m.histogram(0) - H_after_hmc
+    W = orc.Weights(sp.e_lo, wl.bin_width, sp.n_bins, b, a, g)
+    H = np.zeros(sp.n_bins, np.uint64)
+    for i in range(n_walk):
+        ow = orc.Walker(s, pos_h[i], i, wl.seed)
+        assert ow.energy == pytest.approx(e_h[i], abs=1e-11)
+        log = np.zeros(n_log, np.uint8)
+        ow.run(W, orc.move_params(wl), n_sweeps, H, accept_log=log)
+        assert np.array_equal(log_g[i], log), f"walker {i}: accept sequence after HMC differs"
+        assert np.allclose(pos_g[i], ow.pos, rtol=0, atol=1e-10)
+        assert e_g[i] == pytest.approx(ow.energy, abs=1e-10)
+        assert cnt["accepted"][i] == ow.counters.accepted
+        assert cnt["sweeps"][i] == n_sweeps
+    assert np.array_equal(H_sweep, H)
+    m.close()
+
+
+def test_hmc_after_fp32_split_sweeps_starts_from_the_fp64_energy(lib, orc):
+    """In the FP32-split mode the running energy of the sweeps drifts from the FP64 energy of the
+    coordinates (no resync here).  The trajectories build H0 from the FP64 energy of the start,
+    so their decisions are those of an FP64 oracle walker started from the GPU's coordinates,
+    and afterwards the walker's energy is exact again (a rejected trajectory keeps the
+    recomputed start energy)."""
+    wl = workloads.batched_chains(n_seq=1, n_min=40, n_max=40)
+    sp = wl.systems[0]
+    n_walk, n_traj, steps, h = 4, 20, 6, 0.03
+    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=n_walk, precision=1,
+                               resync_sweeps=0)
+    b, a, g = _canonical(sp, wl, 0.7)
+    m.set_weights(0, b, a, g)
+    m.sweep(3000)
+    pos0, e0, _ = m.walkers_state(0)
+    s = orc.System.from_workload(wl)
+    drift = np.array([abs(e0[i] - s.energy(pos0[i])) for i in range(n_walk)])
+    print("running-energy drift before HMC", drift)
+    assert drift.max() > 1e-9, "no drift to test against"
+    H0 = m.histogram(0).copy()
+    m.hmc(n_traj, steps, h)
+    pos_g, e_g, cnt = m.walkers_state(0)
+    W = orc.Weights(sp.e_lo, wl.bin_width, sp.n_bins, b, a)
+    H = np.zeros(sp.n_bins, np.uint64)
+    for i in range(n_walk):
+        w = HM.HmcWalker(s, pos0[i], i, wl.seed)
+        for _ in range(n_traj):
+            w.trajectory(W, steps, h, H)
+        assert cnt["hmc_accepted"][i] == w.accepted, (i, cnt["hmc_accepted"][i], w.accepted)
+        assert np.allclose(pos_g[i], w.pos, rtol=0, atol=1e-8)
+        _, _, sc = s.energy_parts(pos_g[i])
+        assert abs(e_g[i] - s.energy(pos_g[i])) <= 1e-11 * max(1.0, sc)
+    assert np.array_equal(m.histogram(0) - H0, H)
     m.close()
 
 
