@@ -164,13 +164,24 @@ __device__ __forceinline__ int wave_min_i(int v) {
 
 __device__ __forceinline__ void set_error(int *err, int code) { atomicCAS(err, 0, code); }
 
+// Bin coordinate t = (e - e_lo) / eps, exactly as the IEEE quotient wherever it decides an
+// integer (the bin, the window test): the product with the rounded reciprocal differs from the
+// quotient by a few ulps (below 1e-11 for t < 10^5), so only a t within 1e-9 of an integer is
+// recomputed by the division itself.  Near edges the branch is rare, elsewhere it costs a
+// compare.
+__device__ __forceinline__ double bin_coord(double e, double e_lo, double eps, double inv_eps) {
+    const double d = e - e_lo;
+    const double t = d * inv_eps;
+    return fabs(t - rint(t)) < 1e-9 ? d / eps : t;
+}
+
 // Bin of energy e in the window [e_lo, e_lo + K eps), or -1.  A walker whose running energy sat
 // at a window edge can be found up to a few 1e-5 outside it by the FP64 resync (FP32 pair terms
 // accumulate rounding between resyncs); energies within kEdgeTol outside the window are kept in
 // the edge bin, so the walker continues from its exact energy.
 constexpr double kEdgeTol = 1e-3;
 __device__ __forceinline__ int window_bin(double e, double e_lo, double eps, double inv_eps, int K) {
-    const double t = (e - e_lo) * inv_eps;
+    const double t = bin_coord(e, e_lo, eps, inv_eps);
     if (t >= 0.0 && t < (double)K) return (int)t;
     if (e >= e_lo - kEdgeTol && e < e_lo + (double)K * eps + kEdgeTol) return t < 0.0 ? 0 : K - 1;
     return -1;

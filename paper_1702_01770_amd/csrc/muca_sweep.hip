@@ -291,7 +291,7 @@ __device__ void run_walker(const SweepArgs &a, const SysDev &sd, int sys, int w,
             }
             const double dE = wave_sum(acc);
             const double En = E + dE;
-            const double t = (En - e_lo) * a.inv_bin;
+            const double t = bin_coord(En, e_lo, a.bin_width, a.inv_bin);
             const bool inwin = (t >= 0.0) && (t < (double)K);
             const int kn = inwin ? (int)t : 0;
             const double2 wn = lnw[kn];
@@ -372,7 +372,7 @@ __device__ void run_walker(const SweepArgs &a, const SysDev &sd, int sys, int w,
                         }
                         const double rdE = wave_sum(racc);
                         const double rEn = E + rdE;
-                        const double rt = (rEn - e_lo) * a.inv_bin;
+                        const double rt = bin_coord(rEn, e_lo, a.bin_width, a.inv_bin);
                         const bool rin = (rt >= 0.0) && (rt < (double)K);
                         const int rkn = rin ? (int)rt : 0;
                         const double2 rw = lnw[rkn];
@@ -514,7 +514,7 @@ __global__ void __launch_bounds__(256) k_walker_energy(SweepArgs a, int n_walker
     const double E = full_energy_fp64<SLOTS, PERIODIC>(a, N, px, py, pz, ux, uy, uz, inf, ctab);
     if (lane == 0) {
         a.energy[w] = E;
-        const double t = (E - sd.e_lo) * a.inv_bin;
+        const double t = bin_coord(E, sd.e_lo, a.bin_width, a.inv_bin);
         if (!(t >= 0.0 && t < (double)sd.n_bins)) set_error(a.err, -4);
     }
 }

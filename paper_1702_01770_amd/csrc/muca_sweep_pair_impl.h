@@ -425,7 +425,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             }
             const double dE = group_sum<G>(acc);
             const double En = E + dE;
-            const double t = (En - e_lo) * inv_eps;
+            const double t = bin_coord(En, e_lo, a.bin_width, inv_eps);
             const bool inwin = (t >= 0.0) && (t < (double)K);
             const int kn = inwin ? (int)t : 0;
             const double lnw_new = lnw_at(L.lw, kn, t);
@@ -505,7 +505,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                         }
                         const double rdE = group_sum<G>(racc);
                         const double rEn = E + rdE;
-                        const double rt = (rEn - e_lo) * inv_eps;
+                        const double rt = bin_coord(rEn, e_lo, a.bin_width, inv_eps);
                         const bool rin = (rt >= 0.0) && (rt < (double)K);
                         const int rkn = rin ? (int)rt : 0;
                         const double rlnw = lnw_at(L.lw, rkn, rt);
@@ -656,7 +656,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                     const double pdE = group_sum<G>(pacc) + djoint;
                     const bool pin = group_sum<G>(outside) == 0.0;
                     const double pEn = E + pdE;
-                    const double pt = (pEn - e_lo) * inv_eps;
+                    const double pt = bin_coord(pEn, e_lo, a.bin_width, inv_eps);
                     const bool pwin = (pt >= 0.0) && (pt < (double)K);
                     const int pkn = pwin ? (int)pt : 0;
                     const double plnw = lnw_at(L.lw, pkn, pt);
@@ -733,7 +733,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                     }
                     const double rdE = group_sum<G>(racc);
                     const double rEn = E + rdE;
-                    const double rt = (rEn - e_lo) * inv_eps;
+                    const double rt = bin_coord(rEn, e_lo, a.bin_width, inv_eps);
                     const bool rin = (rt >= 0.0) && (rt < (double)K);
                     const int rkn = rin ? (int)rt : 0;
                     const double rlnw = lnw_at(L.lw, rkn, rt);
