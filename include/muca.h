@@ -270,6 +270,23 @@ size_t muca_reweight_workspace_bytes(int64_t n, int32_t n_t);
 int muca_reweight_fwd(const double *energy, const double *lnw0, int64_t n, const double *temps,
                       int32_t n_t, double *mean, double *cv, double *moments, void *workspace,
                       size_t workspace_bytes, void *stream);
+/*
+ * Allocation-free variant of muca_reweight_fwd, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, kernels and results as muca_reweight_fwd, but the workspace is a static device
+ * array of MUCA_REWEIGHT_STATIC_BYTES inside the library, one per GPU, held until the process
+ * ends; the call itself allocates and frees nothing.  Requires
+ * muca_reweight_workspace_bytes(n, n_t) <= MUCA_REWEIGHT_STATIC_BYTES (e.g. up to about 4.2e6
+ * samples at 64 temperatures, 1.05e6 at 256), else MUCA_E_INVAL.  Runs on the current HIP
+ * device, which must be the one that owns the pointers and the stream.  All calls on one GPU
+ * share its array: calls that overlap in time on that GPU (different streams, or host threads
+ * without ordering) race and give wrong results; calls ordered on one stream are safe.
+ */
+#define MUCA_REWEIGHT_STATIC_BYTES (4u << 20)
+int muca_reweight_fwd_noalloc(const double *energy, const double *lnw0, int64_t n,
+                              const double *temps, int32_t n_t, double *mean, double *cv,
+                              double *moments, void *stream);
+
 /* grad_mean, grad_cv: device [n_t] upstream gradients; grad_e: device [n] receives
  * d(sum_T grad_mean <E>_T + grad_cv C_V(T)) / dE_s. */
 int muca_reweight_bwd(const double *energy, const double *lnw0, int64_t n, const double *temps,

@@ -245,6 +245,15 @@ def reweight_fwd(e_ptr, lnw0_ptr, n, temps, mean_ptr, cv_ptr, mom_ptr, ws_ptr, w
                                    int(ws_bytes), C.c_void_p(stream)))
 
 
+def reweight_fwd_noalloc(e_ptr, lnw0_ptr, n, temps, mean_ptr, cv_ptr, mom_ptr, stream):
+    """muca_reweight_fwd with the library's static per-GPU workspace (no allocation)."""
+    t = np.ascontiguousarray(temps, dtype=np.float64)
+    check(load().muca_reweight_fwd_noalloc(C.c_void_p(e_ptr), C.c_void_p(lnw0_ptr), int(n),
+                                           _ptr(t, C.c_double), len(t), C.c_void_p(mean_ptr),
+                                           C.c_void_p(cv_ptr), C.c_void_p(mom_ptr),
+                                           C.c_void_p(stream)))
+
+
 def reweight_bwd(e_ptr, lnw0_ptr, n, temps, mom_ptr, gmean_ptr, gcv_ptr, ge_ptr, stream):
     t = np.ascontiguousarray(temps, dtype=np.float64)
     check(load().muca_reweight_bwd(C.c_void_p(e_ptr), C.c_void_p(lnw0_ptr), int(n),

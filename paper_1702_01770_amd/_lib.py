@@ -77,7 +77,8 @@ EXPORTS = ["muca_init", "muca_sweep", "muca_hmc", "muca_update_weights", "muca_i
            "muca_set_accept_log", "muca_get_accept_log", "muca_get_state", "muca_set_state",
            "muca_get_launch_info",
            "muca_autotune", "muca_energy_fwd", "muca_energy_bwd",
-           "muca_reweight_workspace_bytes", "muca_reweight_fwd", "muca_reweight_bwd",
+           "muca_reweight_workspace_bytes", "muca_reweight_fwd", "muca_reweight_fwd_noalloc",
+           "muca_reweight_bwd",
            "microcanonical_analyze", "muca_last_error", "muca_destroy"]
 
 _lib = None
@@ -121,6 +122,7 @@ def load():
     L.muca_reweight_workspace_bytes.restype = C.c_size_t
     L.muca_reweight_workspace_bytes.argtypes = [i64, i32]
     L.muca_reweight_fwd.argtypes = [vp, vp, i64, _DP, i32, vp, vp, vp, vp, C.c_size_t, vp]
+    L.muca_reweight_fwd_noalloc.argtypes = [vp, vp, i64, _DP, i32, vp, vp, vp, vp]
     L.muca_reweight_bwd.argtypes = [vp, vp, i64, _DP, i32, vp, vp, vp, vp, vp]
     L.microcanonical_analyze.argtypes = [C.POINTER(AnalysisIn), C.POINTER(AnalysisOut)]
     L.muca_last_error.restype = C.c_char_p

@@ -5,6 +5,7 @@
 // 1, E, E^2, each reduced in a fixed order.  Backward: one thread per sample loops over T.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <string>
 
 #include "../../include/muca.h"
@@ -186,6 +187,39 @@ hipError_t launch_reweight_bwd(const double *energy, const double *lnw0, long lo
     return hipGetLastError();
 }
 
+// Workspace of the allocation-free forward pass: a file-scope device array, one copy per GPU
+// (held until the process ends) and shared by every call on that GPU.  Its name is only a
+// host-side stand-in: kernels get the device address that hipGetSymbolAddress returns for the
+// current device, looked up once per device and kept.  Every element the forward pass reads
+// (block maxima, partial sums, global maxima) is written by an earlier kernel of the same call,
+// so nothing needs clearing between calls.
+constexpr size_t kRwStaticBytes = MUCA_REWEIGHT_STATIC_BYTES;
+static __device__ __align__(256) double scratch[kRwStaticBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of this GPU's scratch array, or null (with the reason in *why).
+static void *scratch_for_current_device(const char **why) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        *why = "no current HIP device (or device index >= 64)";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            *why = hipGetErrorString(e);
+            return nullptr;
+        }
+        g_scratch_dev[dev] = p;
+    }
+    return g_scratch_dev[dev];
+}
+
 }  // namespace muca
 
 extern "C" {
@@ -212,6 +246,40 @@ int muca_reweight_fwd(const double *energy, const double *lnw0, int64_t n, const
     }
     const hipError_t e = launch_reweight_fwd(energy, lnw0, n, temps, n_t, mean, cv, moments,
                                              workspace, (hipStream_t)stream);
+    if (e != hipSuccess) { set_global_error(hipGetErrorString(e)); return MUCA_E_DEVICE; }
+    return MUCA_OK;
+}
+
+int muca_reweight_fwd_noalloc(const double *energy, const double *lnw0, int64_t n,
+                              const double *temps, int32_t n_t, double *mean, double *cv,
+                              double *moments, void *stream) {
+    using namespace muca;
+    if (!energy || !lnw0 || !temps || !mean || !cv || !moments || n < 1 || n_t < 1 ||
+        n_t > kRwMaxT) {
+        set_global_error("muca_reweight_fwd_noalloc: bad arguments (need n >= 1, 1 <= n_t <= 256)");
+        return MUCA_E_INVAL;
+    }
+    for (int i = 0; i < n_t; ++i)
+        if (!(temps[i] > 0.0)) {
+            set_global_error("muca_reweight_fwd_noalloc: temperatures must be > 0");
+            return MUCA_E_INVAL;
+        }
+    const size_t need = reweight_workspace_bytes(n, n_t);
+    if (need > kRwStaticBytes) {
+        set_global_error(("muca_reweight_fwd_noalloc: " + std::to_string(n) + " samples at " +
+                          std::to_string(n_t) + " temperatures need " + std::to_string(need) +
+                          " bytes of workspace, more than the static " +
+                          std::to_string(kRwStaticBytes) + "; use muca_reweight_fwd").c_str());
+        return MUCA_E_INVAL;
+    }
+    const char *why = "";
+    void *ws = scratch_for_current_device(&why);
+    if (!ws) {
+        set_global_error((std::string("muca_reweight_fwd_noalloc: scratch lookup failed: ") + why).c_str());
+        return MUCA_E_DEVICE;
+    }
+    const hipError_t e = launch_reweight_fwd(energy, lnw0, n, temps, n_t, mean, cv, moments, ws,
+                                             (hipStream_t)stream);
     if (e != hipSuccess) { set_global_error(hipGetErrorString(e)); return MUCA_E_DEVICE; }
     return MUCA_OK;
 }
