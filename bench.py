@@ -1,15 +1,22 @@
 """Benchmark: multicanonical (MUCA) trial moves per second on one MI355X.
 
-Workload (synthetic stand-in for the paper's chains, see workloads.batched_chains): 32 single-chain
-AB systems with lengths drawn uniformly from 13..55 (~60 % A), 128 walkers per system (4096
-walkers), bin width 0.05 over [-4N, +N), FP32 pair arithmetic with FP64 energies / weights.
+Headline workload (synthetic stand-in for the paper's chains, see workloads.batched_chains): 32
+single-chain AB systems with lengths drawn uniformly from 13..55 (~60 % A), 128 walkers per system
+(4096 walkers), bin width 0.05 over [-4N, +N), FP32 pair arithmetic with FP64 energies / weights.
 One step = one MUCA iteration: --sweeps sweeps of every walker followed by the Berg weight
 update, replayed from a captured HIP graph (persistent sweep launches + update kernel).
 
-Printed JSON line: value = single-bead trial moves per second over all walkers (batched form),
-plus the plain form (one walker per system, same kernels) for comparison, the roofline of the
-sweep kernel (algorithmic FP32/FP64 ALU operations per launch over the launch time measured
-with HIP events on the library's stream) and the FP64 CPU oracle timed on a bounded sample.
+Printed JSON line: value = single-bead trial moves per second over all walkers of that workload,
+the roofline of its sweep kernel (algorithmic FP32/FP64 ALU operations per launch over the launch
+time measured with HIP events on the library's stream), and beside it:
+  * matched_error: the plain (one walker) and batched (4096 walkers sharing ln W) forms on the
+    13-bead chain, each run until its entropy is as close to the FP64 oracle's reference as the
+    oracle's own replicas get at that chain's budget (tests/golden/muca_c1_reference.json):
+    moves/s and GPU time to that target for both forms;
+  * configs: throughput of the aggregation (4 x 9 beads) and cross-seeding (76 beads) workloads
+    and of the headline workload in FP64;
+  * cpu_baseline: the FP64 oracle on the host cores (one core, median of five, and one process
+    per core, pinned) running the same evolving-weight MUCA scheme on a bounded sample.
 """
 from __future__ import annotations
 
@@ -25,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (published, packed)
+PEAK_FP64_TFLOPS = 78.6       # MI355X vector FP64 (published)
 
 
 def algorithmic_flops_per_move(n_beads: int, n_chains: int = 1, periodic: bool = False,
@@ -38,6 +46,27 @@ def algorithmic_flops_per_move(n_beads: int, n_chains: int = 1, periodic: bool =
     partners = n_beads - 1 - bonded
     per_pair = 2 * (13 + (9 if periodic else 0)) + 2
     return partners * per_pair + 50 + 60 + (56 if torsion else 0)
+
+
+def rigid_flops(chain_len: int, n_beads: int, periodic: bool = True) -> float:
+    """Operations of one rigid translation of a chain of chain_len beads among n_beads: every
+    inter-chain pair of the moved chain evaluated before and after (13, +9 periodic, each), their
+    difference and accumulation (2), plus the shift and the acceptance (60)."""
+    pairs = chain_len * (n_beads - chain_len)
+    return pairs * (2 * (13 + (9 if periodic else 0)) + 2) + 60
+
+
+def workload_flops_per_sweep(wl, sp) -> float:
+    """Algorithmic operations of one sweep of one walker of system sp: N single-bead moves and
+    the rigid translations of a multi-chain system."""
+    periodic = wl.box_kind == 2
+    torsion = wl.k_tors != 0.0
+    f = sp.n_beads * algorithmic_flops_per_move(sp.n_beads, len(sp.chain_len), periodic, torsion)
+    if len(sp.chain_len) > 1 and wl.rigid_per_sweep:
+        # the translated chain is drawn uniformly from the system's chains
+        f += wl.rigid_per_sweep * float(np.mean([rigid_flops(n, sp.n_beads, periodic)
+                                                 for n in sp.chain_len]))
+    return f
 
 
 _STREAMS = []
@@ -89,61 +118,190 @@ def run_gpu(wl, walkers, n_sweeps, steps, warmup, stream, autotune=True, **launc
                 acc_rate=float(np.sum(cnt["accepted"]) / max(1, np.sum(cnt["moves"]))))
 
 
-def matched_error(stream):
-    """Batched vs plain at the same statistics per MUCA iteration, on the 6-bead chain whose
-    FP64-oracle replica statistics are stored in tests/golden/muca_n6_reference.json.  Plain: one
-    walker doing all sweeps of an iteration; batched: 64 walkers sharing the weights, each doing
-    1/64 of them.  Reports the S(E) error of each against the oracle replica mean (RMS over the
-    grid, in units of the oracle's replica standard deviation) and the GPU time of each run."""
+def _grid_entropy(beta, alpha, e_lo, eps, k_lo, k_hi):
+    """S_n(E) = beta_k E - alpha_k (Eq. 8) at the centres of bins [k_lo, k_hi), zero at the top."""
+    k = np.arange(k_lo, k_hi)
+    E = e_lo + (k + 0.5) * eps
+    S = beta[k] * E - alpha[k]
+    return S - S[-1]
+
+
+def _aligned_error(S, S_ref, sigma, lo):
+    """max over the converged grid points [lo, top) of |S - S_ref - c|, c the offset that
+    minimises the sum of ((S - S_ref - c) / sigma)^2."""
+    sl = slice(lo, len(S_ref) - 1)
+    d = S[sl] - S_ref[sl]
+    w = 1.0 / sigma[sl] ** 2
+    c = float(np.sum(w * d) / np.sum(w))
+    return float(np.max(np.abs(d - c)))
+
+
+def matched_error(stream, plain_reps=16, plain_sweeps=100_000, max_plain_iters=20,
+                  batched_walkers=4096, batched_sweeps=250, batched_reps=4,
+                  max_batched_iters=50, eq_sweeps=300):
+    """Plain vs batched form of MUCA at matched S(E) error on the 13-bead chain (FP64).
+
+    Target: the aligned entropy error the FP64 oracle reaches at that chain's budget (one walker,
+    ten iterations of 10^5 sweeps), as the median over its replicas, measured against a longer
+    parallel-MUCA oracle reference on the grid range where that reference has converged; all of
+    it is read from tests/golden/muca_c1_reference.json (written from the oracle only).
+    Plain form: one walker, iterations of 10^5 sweeps; `plain_reps` independent replicas run
+    side by side (one wave each), exactly the schedule of the oracle's replicas, and each stops
+    the clock when its error first reaches the target (a replica trapped in compact states may
+    never reach it; its time counts as infinite in the median).  Batched form: `batched_walkers`
+    walkers sharing ln W, one replica after another: every walker first thermalises for
+    `eq_sweeps` sweeps at W = 1 whose statistics are discarded (all walkers start from the
+    straight chain, and with few sweeps per walker that start would bias the first histogram,
+    which Berg's accumulation keeps weighting), then iterations of `batched_sweeps` sweeps per
+    walker.  Times are GPU times of the thermalisation and the MUCA iterations (sweeps + weight
+    update) from HIP events on the library's stream; the error checks run on the host in
+    between."""
     import torch
 
     import paper_1702_01770_amd as P
     import workloads
-    ref = json.load(open(os.path.join(ROOT, "tests", "golden", "muca_n6_reference.json")))
-    oS = np.array([c["S"] for c in ref["curves"]])
-    o_mean, o_sd = oS.mean(axis=0), oS.std(axis=0, ddof=1)
-    total = ref["walkers"] * ref["sweeps"]
-    iters, block, k_lo, k_hi = ref["iterations"], ref["block"], ref["k_lo"], ref["k_hi"]
-    out = {}
-    for name, walkers in (("plain", 1), ("batched", 64)):
-        wl = workloads.single_chain(n=6)
-        sp = wl.systems[0]
-        reps = 4
-        wl.systems = [sp] * reps                       # 4 independent replicas at once
-        m = P.Muca.from_workload(wl, workloads.initial_positions(workloads.single_chain(n=6)) * reps,
-                                 walkers=walkers, precision=1, seed=77_000_003,
-                                 resync_sweeps=100, stream=stream.cuda_stream)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        bs = [[] for _ in range(reps)]
-        al = [[] for _ in range(reps)]
-        ms_total = 0.0
-        for _ in range(iters):
-            e0.record(stream)
-            m.sweep(total // walkers)
-            e1.record(stream)
-            m.update_weights()
-            e1.synchronize()
-            ms_total += e0.elapsed_time(e1)
-            for r in range(reps):
-                b, a, _ = m.weights(r)
-                bs[r].append(b)
-                al[r].append(a)
+    ref = json.load(open(os.path.join(ROOT, "tests", "golden", "muca_c1_reference.json")))
+    rr = ref["reference"]
+    S_ref, sigma = np.array(rr["S"]), np.array(rr["replica_sigma"])
+    lo, target = rr["converged_from"], ref["target"]["delta_S"]
+    k_lo, k_hi = ref["k_lo"], ref["k_hi"]
+    wl0 = workloads.single_chain()
+    sp = wl0.systems[0]
+    N = sp.n_beads
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def one_iteration(m, sweeps):
+        e0.record(stream)
+        m.iterate(sweeps, 1)
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    def thermalise(m, n_sys):
+        if not eq_sweeps:
+            return 0.0
+        dt = one_iteration(m, eq_sweeps)
+        zero = np.zeros(sp.n_bins)
+        for r in range(n_sys):
+            m.set_weights(r, zero, zero, zero)        # back to W = 1, statistics discarded
+        return dt
+
+    def errors(m, n_sys):
+        out = []
+        for r in range(n_sys):
+            b, a, _ = m.weights(r)
+            out.append(_aligned_error(_grid_entropy(b, a, sp.e_lo, wl0.bin_width, k_lo, k_hi),
+                                      S_ref, sigma, lo))
+        return out
+
+    # plain: replicas as independent systems of one context, one walker each
+    wl = workloads.single_chain()
+    wl.systems = [sp] * plain_reps
+    m = P.Muca.from_workload(wl, workloads.initial_positions(wl0) * plain_reps, walkers=1,
+                             precision=0, seed=55_000_001, stream=stream.cuda_stream)
+    hit, hit_it, plain_s, p_trace = [None] * plain_reps, [None] * plain_reps, [], []
+    t_cum = 0.0
+    for it in range(max_plain_iters):
+        dt = one_iteration(m, plain_sweeps)
+        t_cum += dt
+        plain_s.append(dt)
+        errs = errors(m, plain_reps)
+        p_trace.append(float(np.median(errs)))
+        for r, e in enumerate(errs):
+            if hit[r] is None and e <= target:
+                hit[r], hit_it[r] = t_cum, it + 1
+        if all(h is not None for h in hit):
+            break
+    m.close()
+    plain_rate = plain_sweeps * N / float(np.median(plain_s))
+    reached = [h for h in hit if h is not None]
+    censored = sorted(h if h is not None else float("inf") for h in hit)
+    plain_median = float(np.median(censored))
+
+    # batched: 4096 walkers sharing the weights of one system
+    b_hit, b_it, b_rate, plan, b_traces = [], [], [], None, []
+    for rep in range(batched_reps):
+        m = P.Muca.from_workload(wl0, workloads.initial_positions(wl0), walkers=batched_walkers,
+                                 precision=0, seed=56_000_001 + 1000 * rep,
+                                 stream=stream.cuda_stream)
+        m.autotune(probe_sweeps=20)           # restores the sampling state afterwards
+        plan = m.launch_info()
+        times, trace = [], []
+        t_cum = thermalise(m, 1)
+        for it in range(max_batched_iters):
+            dt = one_iteration(m, batched_sweeps)
+            t_cum += dt
+            times.append(dt)
+            e = errors(m, 1)[0]
+            trace.append(e)
+            if e <= target:
+                b_hit.append(t_cum)
+                b_it.append(it + 1)
+                break
+        b_traces.append(trace[:12])
+        b_rate.append(batched_walkers * batched_sweeps * N / float(np.median(times)))
         m.close()
-        errs = []
-        for r in range(reps):
-            res = P.microcanonical_analyze(np.array(bs[r]), np.array(al[r]), sp.e_lo,
-                                           wl.bin_width, k_lo, k_hi, iters - block, iters,
-                                           block, wl.bin_width, beta_c=1.0)
-            d = (res["S"] - o_mean)[:-1] / o_sd[:-1]
-            errs.append(float(np.sqrt(np.mean(d * d))))
-        out[name] = {"walkers": walkers, "sweeps_per_walker_per_iter": total // walkers,
-                     "gpu_ms_per_iter": ms_total / iters,
-                     "S_rms_err_in_oracle_sd": float(np.mean(errs))}
-    out["time_ratio_plain_over_batched"] = (out["plain"]["gpu_ms_per_iter"] /
-                                            out["batched"]["gpu_ms_per_iter"])
-    out["system"] = "single chain N=6 (workloads.single_chain(n=6)), 4 replicas per form"
+    out = {
+        "system": "single 13-bead AB chain (workloads.single_chain), FP64, window [-52, 13)",
+        "target": {"delta_S": target, "definition": "median aligned S(E) error of the FP64 "
+                   "oracle's replicas at 1 walker x 10 iterations x 1e5 sweeps, against a "
+                   "16-run parallel-MUCA oracle reference, on bins from E = "
+                   f"{rr['converged_e']:.3f} to the window top"},
+        "plain": {"walkers": 1, "sweeps_per_iteration": plain_sweeps, "replicas": plain_reps,
+                  "max_iterations": max_plain_iters, "moves_per_s": plain_rate,
+                  "reached": len(reached),
+                  "time_to_target_s": plain_median if np.isfinite(plain_median) else None,
+                  "time_to_target_s_of_those_reaching": float(np.median(reached))
+                  if reached else None,
+                  "time_at_oracle_budget_s": 10 * float(np.median(plain_s)),
+                  "iterations_to_target": float(np.median([i for i in hit_it if i]))
+                  if reached else None, "median_error_by_iteration": p_trace},
+        "batched": {"walkers": batched_walkers, "sweeps_per_walker_per_iteration": batched_sweeps,
+                    "replicas": batched_reps, "moves_per_s": float(np.median(b_rate)),
+                    "reached": len(b_hit),
+                    "time_to_target_s": float(np.median(b_hit)) if b_hit else None,
+                    "iterations_to_target": float(np.median(b_it)) if b_it else None,
+                    "error_by_iteration": b_traces, "launch_plan": plan},
+        "thermalisation_sweeps": eq_sweeps,
+    }
+    if b_hit:
+        # the plain form's median time to the target; when fewer than half of its replicas get
+        # there within max_plain_iters, the time of the oracle's own budget (ten iterations, at
+        # which half of the oracle's replicas are within the target by its definition)
+        t_plain = out["plain"]["time_to_target_s"] or out["plain"]["time_at_oracle_budget_s"]
+        out["time_ratio_plain_over_batched"] = t_plain / out["batched"]["time_to_target_s"]
+    out["moves_per_s_ratio_batched_over_plain"] = out["batched"]["moves_per_s"] / plain_rate
     return out
+
+
+def config_leg(name, wl, sweeps, steps, warmup, stream, precision=None):
+    """Throughput of one workload: single-bead moves/s over all walkers (plus rigid moves) and
+    the algorithmic operations per second against the vector peak of the arithmetic it runs in
+    (FP32 pair terms: 157.3 TFLOP/s; FP64: 78.6), autotuned, timed over `steps` MUCA
+    iterations after `warmup`."""
+    import dataclasses
+    if precision is not None:
+        wl = dataclasses.replace(wl, precision=precision,
+                                 resync_sweeps=wl.resync_sweeps if precision else 0)
+    r = run_gpu(wl, wl.walkers_per_system, sweeps, steps, warmup, stream)
+    sec = r["event_ms"] / 1e3
+    W = wl.walkers_per_system
+    flops = sum(W * sweeps * steps * workload_flops_per_sweep(wl, sp) for sp in wl.systems)
+    rigid = sum(W * sweeps * steps * wl.rigid_per_sweep for sp in wl.systems
+                if len(sp.chain_len) > 1)
+    fp32 = wl.precision == 1
+    peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
+    achieved = flops / sec / 1e12
+    return {"workload": name, "walkers": W * len(wl.systems),
+            "precision": "f32 pair terms + f64 energy/weights" if fp32 else "f64",
+            "sweeps_per_step": sweeps, "steps": steps, "ms_per_step": r["event_ms"] / steps,
+            "moves_per_s": r["moves"] / sec, "rigid_moves_per_s": rigid / sec,
+            "acceptance": r["acc_rate"],
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                         "frac": achieved / peak},
+            "sweep_launch": {"launches": r["launches"], "avg_ms": r["event_ms"] / r["launches"]},
+            "launch_plan": r["plan"]}
 
 
 def chain_moves_leg(wl, stream, sweeps=2000, steps=2):
@@ -191,24 +349,18 @@ PAPER_MAXWELL = {"cross_human": {"latent": 0.513, "barrier": 0.034},
 PAPER_SWEEPS_PER_ITERATION = {"abeta_dimer": 10 ** 6, "cross_human": 10 ** 7, "cross_rat": 10 ** 7}
 
 
-def paper_physics_leg(stream, names, iters=1000, walkers=4096, first=700, block=25,
-                      hmc_traj=0, hmc_steps=10, hmc_step=0.01, reset_every=0, e_hi=None):
+def paper_physics_leg(stream, names, iters=1000, walkers=4096, first=700, block=25):
     """Full multicanonical runs of the paper's example systems as in Sec. 4: `walkers` walkers
     share the paper's sweeps per iteration, `iters` Berg iterations, then the
     microcanonical analysis (Eqs. 4-8) of iterations [first, iters) in blocks of `block`:
     Maxwell construction on beta(eps), latent heat and free-energy barrier per monomer, and
     whether the caloric curve bends back (a region of negative microcanonical specific heat).
-    Flatness per iteration as the paper judges it: c_var < 5 % and peaks within 20 %.  With
-    hmc_traj > 0 every iteration also runs that many hybrid Monte Carlo trajectories per walker
-    (hmc_steps leapfrog steps of hmc_step) before the weight update.  With reset_every > 0 the
-    recursion's accumulated statistics g are cleared every reset_every iterations before the
-    analysed range, so estimates from the early, far-from-equilibrium iterations stop weighing
-    on the weights.  e_hi (total energy) moves the window's upper edge from +N."""
+    Flatness per iteration as the paper judges it: c_var < 5 % and peaks within 20 %."""
     import paper_1702_01770_amd as P
     import workloads
     out = {}
     for name in names:
-        wl = workloads.paper_system(name, walkers=walkers, e_hi=e_hi)
+        wl = workloads.paper_system(name, walkers=walkers)
         sp = wl.systems[0]
         sweeps = -(-PAPER_SWEEPS_PER_ITERATION[name] // walkers)
         m = P.Muca.from_workload(wl, workloads.initial_positions(wl),
@@ -218,15 +370,8 @@ def paper_physics_leg(stream, names, iters=1000, walkers=4096, first=700, block=
         A = np.zeros((iters, sp.n_bins))
         t0 = time.perf_counter()
         for it in range(iters):
-            if hmc_traj > 0:
-                m.sweep(sweeps)
-                m.hmc(hmc_traj, hmc_steps, hmc_step)
-                m.update_weights()
-            else:
-                m.iterate(sweeps, 1)
-            B[it], A[it], g_now = m.weights(0)
-            if reset_every > 0 and it < first and (it + 1) % reset_every == 0:
-                m.set_weights(0, B[it], A[it], np.zeros_like(g_now))
+            m.iterate(sweeps, 1)
+            B[it], A[it], _ = m.weights(0)
             if (it + 1) % 50 == 0:
                 st = m.stats_history(it, 1)[0, 0]
                 print(f"[physics] {name} iteration {it + 1}/{iters} cvar {st[1]:.3f} "
@@ -252,8 +397,7 @@ def paper_physics_leg(stream, names, iters=1000, walkers=4096, first=700, block=
         rec = {"beads": sp.n_beads, "sphere_radius": wl.box_len, "iterations": iters,
                "window": [sp.e_lo, sp.e_lo + sp.n_bins * wl.bin_width],
                "sweeps_per_iteration": sweeps * wl.walkers_per_system,
-               "walkers": walkers, "hmc_trajectories_per_iteration": hmc_traj,
-               "recursion_reset_every": reset_every,
+               "walkers": walkers,
                "flat_iterations": int(flat.sum()), "flat_from": conv,
                "last_cvar_full_range": float(st[-1, 1]), "last_cvar_analysed_range": inner_cvar,
                "eps_range": [float(res["E"][0]), float(res["E"][-1])],
@@ -431,35 +575,72 @@ def differentiation_leg(stream, n_cfg=1_000_000, n_t=64, steps=3, warmup=1, samp
             "mean_E_at_T": [float(mean[0]), float(mean[-1])]}
 
 
-def cpu_baseline(wl, target_s: float = 15.0):
-    """FP64 oracle on one host core: one walker of every system, sweeps sized to ~target_s."""
+def _cpu_muca_sample(args):
+    """One oracle process: one walker of every system of the workload (walker id `walker`), run
+    through `iters` MUCA iterations of `sweeps` sweeps with a Berg update of each system's
+    weights after every iteration (the evolving-weight scheme the GPU leg times).  Optionally
+    pinned to one core.  Returns (single-bead moves, seconds)."""
+    walker, iters, sweeps, cpu = args
+    if cpu is not None:
+        os.sched_setaffinity(0, {cpu})
     import oracle
     import workloads
-    oracle.build(force=False)
+    wl = workloads.batched_chains()
     pos0 = workloads.initial_positions(wl)
-    walkers = []
+    mv = oracle.move_params(wl)
+    runs = []
     for s, sp in enumerate(wl.systems):
         sysd = oracle.System.from_workload(wl, s)
-        walkers.append((oracle.Walker(sysd, pos0[s], s * wl.walkers_per_system, wl.seed),
-                        oracle.Weights(sp.e_lo, wl.bin_width, sp.n_bins), sp))
-    mv = oracle.move_params(wl)
-
-    def sweep_all(n):
-        moves = 0
-        t0 = time.perf_counter()
-        for w, W, sp in walkers:
+        runs.append((oracle.Walker(sysd, pos0[s], s * wl.walkers_per_system + walker, wl.seed),
+                     oracle.Weights(sp.e_lo, wl.bin_width, sp.n_bins), sp))
+    moves = 0
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        for w, W, sp in runs:
             H = np.zeros(sp.n_bins, np.uint64)
             before = w.counters.moves
-            w.run(W, mv, n, H)
+            w.run(W, mv, sweeps, H)
             moves += w.counters.moves - before
-        return moves, time.perf_counter() - t0
+            W.berg_update(H)
+    return moves, time.perf_counter() - t0
 
-    m0, t0 = sweep_all(10)
-    n = max(10, int(10 * target_s / max(t0, 1e-3)))
-    m1, t1 = sweep_all(n)
-    return dict(value=m1 / t1, unit="moves/s", cores=1, kind="oracle",
-                sample=f"1 walker of each of the {len(wl.systems)} systems x {n} sweeps "
-                       f"({m1} single-bead moves, {t1:.1f} s, flat weights)")
+
+def cpu_baseline(target_s: float = 4.0, repeats: int = 5, max_procs: int = 16):
+    """The FP64 oracle as it stands on the host: (a) one core, `repeats` runs of a sample sized
+    to about target_s seconds, median rate; (b) one process per core (at most max_procs, the
+    host share of one GPU), each pinned to its own core with its own walker ids, the paper's
+    rank-per-core parallel scheme (Sec. 2.2) without the histogram merge; summed rate."""
+    import multiprocessing as mp
+    import oracle
+    oracle.build(force=False)
+    iters = 3
+    m0, t0 = _cpu_muca_sample((0, 1, 20, None))
+    sweeps = max(20, int(20 * target_s / max(t0, 1e-3) / iters))
+    single = [_cpu_muca_sample((0, iters, sweeps, None)) for _ in range(repeats)]
+    rates = [mv / t for mv, t in single]
+    cpus = sorted(os.sched_getaffinity(0))
+    P = min(len(cpus), max_procs)
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(P) as pool:
+        par = pool.map(_cpu_muca_sample, [(p + 1, iters, sweeps, cpus[p]) for p in range(P)])
+    summed = sum(mv / t for mv, t in par)
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(value=summed, unit="moves/s", cores=P, kind="oracle",
+                sample=f"each process: 1 walker of each of the 32 systems of the headline "
+                       f"workload, {iters} MUCA iterations x {sweeps} sweeps with a Berg "
+                       f"update after each ({single[0][0]} single-bead moves, about "
+                       f"{single[0][1]:.1f} s); {P} processes pinned one per core",
+                single_core={"moves_per_s_median": float(np.median(rates)),
+                             "runs": [float(r) for r in rates]},
+                per_process_moves_per_s=[float(mv / t) for mv, t in par],
+                nproc=os.cpu_count(), affinity_cpus=len(cpus), cpu_model=model)
 
 
 def copy_calibration(n_mib: int = 512, reps: int = 3):
@@ -506,6 +687,9 @@ def sweep_traffic():
     return rec["bytes_per_launch"] if rec else None
 
 
+LEGS = ("matched", "configs", "pivots", "paper", "hmc", "diff", "cpu")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -514,26 +698,14 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--sweeps", type=int, default=100000, help="sweeps per MUCA iteration")
-    ap.add_argument("--plain-sweeps", type=int, default=20000)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-matched", action="store_true")
-    ap.add_argument("--no-chain", action="store_true", help="skip the pivot leg")
-    ap.add_argument("--no-diff", action="store_true", help="skip the differentiation leg")
-    ap.add_argument("--no-paper", action="store_true", help="skip the paper-systems leg")
-    ap.add_argument("--no-hmc", action="store_true", help="skip the hybrid Monte Carlo leg")
+    ap.add_argument("--skip", default="", help="comma-separated legs to skip: " + ",".join(LEGS))
+    ap.add_argument("--only", default="",
+                    help="run only this leg (main, matched, c3, c4, c2_fp64, pivots, paper, hmc, "
+                         "diff, cpu) and print it alone (profiling)")
     ap.add_argument("--paper-physics", default="",
                     help="comma-separated paper systems: only run their full MUCA + analysis")
     ap.add_argument("--physics-iters", type=int, default=1000)
     ap.add_argument("--physics-walkers", type=int, default=4096)
-    ap.add_argument("--physics-ehi", type=float, default=None,
-                    help="upper edge of the energy window (total energy) in the physics leg")
-    ap.add_argument("--physics-reset", type=int, default=0,
-                    help="clear the recursion's accumulated statistics every N iterations")
-    ap.add_argument("--physics-hmc", type=int, default=0,
-                    help="hybrid MC trajectories per walker and iteration in the physics leg")
-    ap.add_argument("--diff-only", action="store_true",
-                    help="run only the differentiation leg (profiling)")
     ap.add_argument("--diff-configs", type=int, default=1_000_000)
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the launch plan given by --walkers-per-wave / --waves-per-block")
@@ -541,7 +713,8 @@ def main():
     ap.add_argument("--waves-per-block", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "the benchmark measures one GPU (no multi-GPU path is implemented); --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark measures one GPU (no multi-GPU path is "
+                                   "implemented); --gpus must be 1"}))
         sys.exit(2)
     import workloads
 
@@ -552,22 +725,37 @@ def main():
     if args.paper_physics:
         print(json.dumps({"paper_physics": paper_physics_leg(
             st, args.paper_physics.split(","), iters=args.physics_iters,
-            walkers=args.physics_walkers, hmc_traj=args.physics_hmc,
-            reset_every=args.physics_reset, e_hi=args.physics_ehi,
-            first=int(0.7 * args.physics_iters), block=max(1, args.physics_iters // 40))}))
+            walkers=args.physics_walkers, first=int(0.7 * args.physics_iters),
+            block=max(1, args.physics_iters // 40))}))
         return
-    if args.diff_only:
-        print(json.dumps({"differentiation": differentiation_leg(st, args.diff_configs,
-                                                                 steps=args.steps,
-                                                                 warmup=args.warmup)}))
+    configs = {
+        "c3": lambda: config_leg("aggregation: 4 x 9 beads, periodic cube L=20, 1024 walkers, "
+                                 "FP32-split, one rigid translation per sweep",
+                                 workloads.aggregation(), 10000, 3, 1, st),
+        "c4": lambda: config_leg("cross-seeding: 4 x 9 + 4 x 10 beads, periodic cube L=25, "
+                                 "bending + torsion, 4096 walkers, FP32-split, one rigid "
+                                 "translation per sweep", workloads.cross_seeding(), 10000, 3,
+                                 1, st),
+        "c2_fp64": lambda: config_leg("batched single chains (the headline workload) in FP64",
+                                      wl, 20000, 3, 1, st, precision=0),
+    }
+    single = dict(configs, matched=lambda: matched_error(st),
+                  pivots=lambda: chain_moves_leg(wl, st), paper=lambda: paper_systems_leg(st),
+                  hmc=lambda: hmc_leg(st),
+                  diff=lambda: differentiation_leg(st, args.diff_configs, steps=args.steps,
+                                                   warmup=args.warmup),
+                  cpu=lambda: cpu_baseline())
+    if args.only and args.only != "main":
+        print(json.dumps({args.only: single[args.only]()}))
         return
+    skip = set(x for x in args.skip.split(",") if x)
     r = run_gpu(wl, wl.walkers_per_system, args.sweeps, args.steps, args.warmup, st,
                 autotune=not args.no_autotune, walkers_per_wave=args.walkers_per_wave,
                 waves_per_block=args.waves_per_block)
     sec = r["event_ms"] / 1e3
     value = r["moves"] / sec
-    flops_per_step = sum(wl.walkers_per_system * args.sweeps * sp.n_beads *
-                         algorithmic_flops_per_move(sp.n_beads) for sp in wl.systems)
+    flops_per_step = sum(wl.walkers_per_system * args.sweeps * workload_flops_per_sweep(wl, sp)
+                         for sp in wl.systems)
     achieved = flops_per_step * args.steps / sec / 1e12
     out = {
         "metric": "MC moves/sec (batched vs plain, 1 GPU) at matched S(E) error vs FP64 oracle",
@@ -588,24 +776,23 @@ def main():
         "acceptance": r["acc_rate"],
         "wall_s": r["wall_s"],
     }
-    if not args.no_plain:
-        rp = run_gpu(wl, 1, args.plain_sweeps, 1, 0, st, autotune=False)
-        plain = rp["moves"] / (rp["event_ms"] / 1e3)
-        out["plain"] = {"value": plain, "unit": "moves/s", "walkers_per_system": 1,
-                        "sweeps": args.plain_sweeps}
-        out["batched_over_plain"] = value / plain
-    if not args.no_matched:
-        out["matched_error"] = matched_error(st)
-    if not args.no_chain:
-        out["with_pivots"] = chain_moves_leg(wl, st)
-    if not args.no_paper:
-        out["paper_systems"] = paper_systems_leg(st)
-    if not args.no_hmc:
-        out["hybrid_mc"] = hmc_leg(st)
-    if not args.no_diff:
+    if args.only == "main":
+        print(json.dumps(out))
+        return
+    if "matched" not in skip:
+        out["matched_error"] = single["matched"]()
+    if "configs" not in skip:
+        out["configs"] = {k: f() for k, f in configs.items()}
+    if "pivots" not in skip:
+        out["with_pivots"] = single["pivots"]()
+    if "paper" not in skip:
+        out["paper_systems"] = single["paper"]()
+    if "hmc" not in skip:
+        out["hybrid_mc"] = single["hmc"]()
+    if "diff" not in skip:
         out["differentiation"] = differentiation_leg(st, args.diff_configs)
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wl)
+    if "cpu" not in skip:
+        out["cpu_baseline"] = single["cpu"]()
     print(json.dumps(out))
 
 

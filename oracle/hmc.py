@@ -92,7 +92,7 @@ class HmcWalker:
     def gen_forces(self, pos, W: Weights):
         """(E, G): energy and generalized forces (suffix sums of -beta(E) dE/dx per chain)."""
         e, g, _ = self.s.energy_grad(pos)
-        k = int(np.clip(np.floor((e - W.e_lo) / W.bin_width), 0, W.n_bins - 1))
+        k = int(np.clip(np.floor((e - W.e_lo) * (1.0 / W.bin_width)), 0, W.n_bins - 1))
         f = -W.beta[k] * g
         G = np.empty_like(f)
         for a, b in zip(self.s.chain_start[:-1], self.s.chain_start[1:]):
@@ -145,7 +145,7 @@ class HmcWalker:
         H0 = -lnw(e0) + 0.5 * float(np.sum(mom * mom))
         v, mom, pos = self.leapfrog(v, mom, W, n_steps, h)
         e1 = self.s.energy(pos)
-        t = (e1 - W.e_lo) / W.bin_width
+        t = (e1 - W.e_lo) * (1.0 / W.bin_width)
         inwin = 0.0 <= t < W.n_bins
         inside = sphere_r2 <= 0.0 or float(np.max(np.sum(pos * pos, axis=1))) <= sphere_r2
         H1 = (-lnw(e1) if inwin else np.inf) + 0.5 * float(np.sum(mom * mom))
@@ -163,7 +163,7 @@ class HmcWalker:
         else:
             self.energy = e0
         if hist is not None:
-            k = int((self.energy - W.e_lo) / W.bin_width)
+            k = int(np.floor((self.energy - W.e_lo) * (1.0 / W.bin_width)))
             hist[min(max(k, 0), W.n_bins - 1)] += 1
         self.traj += 1
         return accept
@@ -178,5 +178,5 @@ class HmcWalker:
 
 def _lnw(W: Weights, e: float) -> float:
     """ln W(E) = -beta_k E + alpha_k in the bin of E (edge bins extended)."""
-    k = int(np.clip(np.floor((e - W.e_lo) / W.bin_width), 0, W.n_bins - 1))
+    k = int(np.clip(np.floor((e - W.e_lo) * (1.0 / W.bin_width)), 0, W.n_bins - 1))
     return -W.beta[k] * e + W.alpha[k]

@@ -261,10 +261,12 @@ static void propose_crank(const double *xp, const double *xb, const double *xn, 
     for (int i = 0; i < 3; ++i) out[i] = xp[i] + (v[i] * c + kxv[i] * sn + k[i] * kv * (1.0 - c));
 }
 
-/* Bin of energy E in the window [e_lo, e_lo + n_bins * bin_width); -1 outside. */
+/* Bin of energy E in the window [e_lo, e_lo + n_bins * bin_width); -1 outside.  The bin is
+ * floor((E - e_lo) * (1 / bin_width)) with the reciprocal rounded once: at a bin edge a quotient
+ * and this product may differ by one bin, and both implementations quantise this way. */
 static int64_t bin_of(const orc_weights *w, double e)
 {
-    double t = (e - w->e_lo) / w->bin_width;
+    double t = (e - w->e_lo) * (1.0 / w->bin_width);
     if (!(t >= 0.0) || !(t < (double)w->n_bins)) return -1;
     return (int64_t)floor(t);
 }

@@ -58,8 +58,6 @@ struct SweepArgs {
     const double *beta, *alpha; // [sum bins]
     unsigned long long *hist;   // [sum bins]
     unsigned int *acc_log;      // [walkers][acc_log_words] or null
-    const unsigned long long *acc_log_base;  // [walkers] single-bead moves done when the log
-                                             // was armed: bit i is the walker's i-th move since
     long long acc_log_moves;
     int acc_log_words;
     int npad;                   // coordinate stride per axis (64 or 128)
@@ -77,6 +75,8 @@ struct SweepArgs {
     int resync_sweeps;
     double drift_tol;
     unsigned int seed_lo, seed_hi;
+    const unsigned long long *acc_log_base;  // [walkers] single-bead moves done when the log
+                                             // was armed: bit i is the walker's i-th move since
 };
 
 // ------------------------------------------------------------------------------------------
@@ -164,15 +164,12 @@ __device__ __forceinline__ int wave_min_i(int v) {
 
 __device__ __forceinline__ void set_error(int *err, int code) { atomicCAS(err, 0, code); }
 
-// Bin coordinate t = (e - e_lo) / eps, exactly as the IEEE quotient wherever it decides an
-// integer (the bin, the window test): the product with the rounded reciprocal differs from the
-// quotient by a few ulps (below 1e-11 for t < 10^5), so only a t within 1e-9 of an integer is
-// recomputed by the division itself.  Near edges the branch is rare, elsewhere it costs a
-// compare.
+// Bin coordinate t = (e - e_lo) * (1 / eps), the reciprocal of the bin width rounded once: the
+// quantiser that decides the bin and the window test, taken the same way by the FP64 reference
+// (at a bin edge a quotient and this product can differ by one bin).
 __device__ __forceinline__ double bin_coord(double e, double e_lo, double eps, double inv_eps) {
-    const double d = e - e_lo;
-    const double t = d * inv_eps;
-    return fabs(t - rint(t)) < 1e-9 ? d / eps : t;
+    (void)eps;
+    return (e - e_lo) * inv_eps;
 }
 
 // Bin of energy e in the window [e_lo, e_lo + K eps), or -1.  A walker whose running energy sat

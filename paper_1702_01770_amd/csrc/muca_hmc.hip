@@ -172,8 +172,8 @@ __device__ double energy_forces(const SweepArgs &a, HmcLds &L, const int *bi, co
 }
 
 // Bin of e, edge bins extended (a non-finite energy maps to bin 0; such an end is rejected).
-__device__ __forceinline__ int bin_of(double e, double e_lo, double eps, int K) {
-    const double t = floor((e - e_lo) / eps);
+__device__ __forceinline__ int bin_of(double e, double e_lo, double inv_eps, int K) {
+    const double t = floor((e - e_lo) * inv_eps);
     if (!(t >= 0.0)) return 0;
     return t >= (double)K ? K - 1 : (int)t;
 }
@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs 
     const bool first = bi_first(inf);
     const int cs = act ? sd.chain_start[bi_chain(inf)] : lane;
     const int ce = act ? sd.chain_start[bi_chain(inf) + 1] - 1 : lane;
-    const double e_lo = sd.e_lo, eps = a.bin_width;
+    const double e_lo = sd.e_lo, inv_eps = a.inv_bin;
     const double *beta = a.beta + sd.bin_off, *alpha = a.alpha + sd.bin_off;
     double *P = a.pos + (size_t)w * 3 * a.npad;
     double E = a.energy[w];
@@ -245,11 +245,11 @@ __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs 
         double gx, gy, gz;
         double Ec = energy_forces<PERIODIC>(a, L, bi, ct, N, lane, ce, gx, gy, gz);
         const double E0 = Ec;
-        const int kb0 = bin_of(E0, e_lo, eps, K);
+        const int kb0 = bin_of(E0, e_lo, inv_eps, K);
         const double H0 = -(-beta[kb0] * E0 + alpha[kb0]) +
                           0.5 * wave_sum_d(mx * mx + my * my + mz * mz);
         auto gen_forces = [&](double Ecur, double &Gx, double &Gy, double &Gz) {
-            const double b = beta[bin_of(Ecur, e_lo, eps, K)];
+            const double b = beta[bin_of(Ecur, e_lo, inv_eps, K)];
             Gx = seg_suffix(-b * gx, lane, cs, ce);
             Gy = seg_suffix(-b * gy, lane, cs, ce);
             Gz = seg_suffix(-b * gz, lane, cs, ce);
@@ -294,12 +294,12 @@ __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs 
         }
         // positions at the end of the trajectory (n_steps >= 1: the last drift wrote them)
         const double nx = L.x[lane], ny = L.y[lane], nz = L.z[lane];
-        const double t1 = (Ec - e_lo) / eps;
+        const double t1 = (Ec - e_lo) * inv_eps;
         const bool inwin = t1 >= 0.0 && t1 < (double)K;
         const bool out = act && a.sphere_r2 > 0.0 && nx * nx + ny * ny + nz * nz > a.sphere_r2;
         const bool inside = __ballot(out) == 0;
         const double K1 = 0.5 * wave_sum_d(mx * mx + my * my + mz * mz);
-        const int k1b = bin_of(Ec, e_lo, eps, K);
+        const int k1b = bin_of(Ec, e_lo, inv_eps, K);
         const double H1 = -(-beta[k1b] * Ec + alpha[k1b]) + K1;
         const U4 ra = philox4x32_10(0u, (unsigned)T, (unsigned)(T >> 32), 8u, k0, k1);
         const bool accept = inwin && inside && (log(u01(ra.x)) < H0 - H1);
@@ -312,7 +312,7 @@ __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs 
             E = E0;                        // the start's FP64 energy replaces the running one
         }
         if (lane == 0) {
-            atomicAdd(&a.hist[sd.bin_off + bin_of(E, e_lo, eps, K)], 1ull);
+            atomicAdd(&a.hist[sd.bin_off + bin_of(E, e_lo, inv_eps, K)], 1ull);
         }
         __builtin_amdgcn_wave_barrier();   // L.x is rewritten by the next trajectory
     }

@@ -200,7 +200,6 @@ __device__ void run_walker(const SweepArgs &a, const SysDev &sd, int sys, int w,
     long long done = 0;
     int m = 0;                       // move index inside the current sweep
     unsigned int *alog = a.acc_log ? a.acc_log + (size_t)w * a.acc_log_words : nullptr;
-    const long long log0 = alog ? (long long)(cnt[C_MOVES] - a.acc_log_base[w]) : 0;
 
     while (done < total) {
         // ---- lane-parallel preparation of the next (up to) 64 single-bead moves ----
@@ -302,7 +301,8 @@ __device__ void run_walker(const SweepArgs &a, const SysDev &sd, int sys, int w,
                 (inwin && inside && (rl_d(lnu_l, i) < lnw_new - lnw_cur)) ? 1 : 0);
             n_wrej += inwin ? 0u : 1u;
             if (alog && accept && lane == 0) {
-                const long long li = log0 + n_mv;
+                // moves since the log was armed (the counter is written back at the launch end)
+                const long long li = (long long)(cnt[C_MOVES] - a.acc_log_base[w]) + n_mv;
                 if (li >= 0 && li < a.acc_log_moves) atomicOr(&alog[li >> 5], 1u << (li & 31));
             }
             ++n_mv;

@@ -298,7 +298,6 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
     long long done = 0;
     int m = 0;
     unsigned int *alog = a.acc_log ? a.acc_log + (size_t)w * a.acc_log_words : nullptr;
-    const long long log0 = alog ? (long long)(cnt[C_MOVES] - a.acc_log_base[w]) : 0;
 
     while (done < total) {
         // ---- each group draws the next (up to) G moves of its walker, one per lane ----
@@ -397,6 +396,9 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 // skip the moved bead itself (d = 0, same chain), its bonded neighbours and empty
                 // lanes
                 const bool use = (j < N) && !(same && (unsigned)(d + 1) <= 2u);
+                // both separations from the FP64 coordinates, each rounded once: taking the new
+                // one as (old - m) in FP32 would carry the rounding of m into every pair at once
+                // (a coherent error F . dm per move that doubled the running-energy drift)
                 double dxo = px[s] - xbx, dyo = py[s] - xby, dzo = pz[s] - xbz;
                 double dxn = px[s] - nx, dyn = py[s] - ny, dzn = pz[s] - nz;
                 if constexpr (PERIODIC) {
@@ -436,7 +438,10 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             const bool accept = inwin && inside && (q.lnu < lnw_new - lnw_cur);
             n_wrej += inwin ? 0u : 1u;
             if (alog && accept && gl == 0) {
-                const long long li = log0 + n_mv;
+                // bit of this move: moves since the log was armed (the walker's move counter is
+                // written back only at the end of the launch); the offset is read here, in the
+                // logging path only, so that no extra state stays live in the move loop
+                const long long li = (long long)(cnt[C_MOVES] - a.acc_log_base[w]) + n_mv;
                 if (li >= 0 && li < a.acc_log_moves) atomicOr(&alog[li >> 5], 1u << (li & 31));
             }
             ++n_mv;

@@ -36,3 +36,28 @@ def test_partners_per_move_match_enumeration():
         per_pair = 2 * 13 + 2
         expect = np.mean(partners) * per_pair + 50 + 60
         assert abs(bench.algorithmic_flops_per_move(n) - expect) < 1e-9
+
+
+def test_multichain_move_and_rigid_counts_match_enumeration():
+    """Several chains (periodic, torsion): a single-bead move's partners are all beads but itself
+    and its bonded neighbours in its own chain; a rigid translation of a chain changes its pairs
+    with every bead of the other chains."""
+    for wl in (workloads.aggregation(), workloads.cross_seeding()):
+        sp = wl.systems[0]
+        lens = sp.chain_len
+        chain = np.concatenate([[c] * n for c, n in enumerate(lens)])
+        n = len(chain)
+        partners = []
+        for b in range(n):
+            bonded = sum(1 for j in (b - 1, b + 1) if 0 <= j < n and chain[j] == chain[b])
+            partners.append(n - 1 - bonded)
+        torsion = wl.k_tors != 0.0
+        expect = np.mean(partners) * (2 * 22 + 2) + 50 + 60 + (56 if torsion else 0)
+        assert abs(bench.algorithmic_flops_per_move(n, len(lens), True, torsion) - expect) < 1e-9
+        rigid_pairs = np.mean([sum(1 for i in range(n) for j in range(n)
+                                   if chain[i] == c and chain[j] != c) for c in range(len(lens))])
+        mean_rigid = np.mean([bench.rigid_flops(c, n) for c in lens])
+        assert abs(mean_rigid - (rigid_pairs * 46 + 60)) < 1e-9
+        assert abs(bench.workload_flops_per_sweep(wl, sp) - (
+            n * bench.algorithmic_flops_per_move(n, len(lens), True, torsion)
+            + wl.rigid_per_sweep * mean_rigid)) < 1e-6
