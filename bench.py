@@ -655,6 +655,20 @@ def copy_calibration(n_mib: int = 512, reps: int = 3):
     return n_mib
 
 
+def flop_calibration(n: int = 1 << 26, reps: int = 3):
+    """Plain FP32 and FP64 elementwise multiplies of known size (one multiply per element): their
+    SQ_INSTS_VALU_MUL_F32 / _F64 counters give the number of element operations one counted
+    instruction stands for (64 for one wave64 instruction without packing), the factor that
+    turns the sweep kernel's instruction counters into FLOP (see profiles/)."""
+    import torch
+    for dt in (torch.float32, torch.float64):
+        a = torch.full((n,), 1.0001, dtype=dt, device="cuda")
+        for _ in range(reps):
+            torch.mul(a, 1.0001, out=a)
+    torch.cuda.synchronize()
+    return n
+
+
 def code_hash(files) -> str:
     """SHA-256 of the given sources with comments and whitespace removed, so that editing a
     comment does not void a measurement of the code."""
@@ -694,6 +708,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run 512 MiB device copies first (counter calibration)")
+    ap.add_argument("--calibrate-flops", action="store_true",
+                    help="run FP32 and FP64 elementwise multiplies first (counter calibration)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=5)
@@ -722,6 +738,8 @@ def main():
     st = make_stream()
     if args.calibrate_copy:
         copy_calibration()
+    if args.calibrate_flops:
+        flop_calibration()
     if args.paper_physics:
         print(json.dumps({"paper_physics": paper_physics_leg(
             st, args.paper_physics.split(","), iters=args.physics_iters,

@@ -57,9 +57,11 @@ struct SweepArgs {
     double *drift;              // [walkers] largest resync drift
     const double *beta, *alpha; // [sum bins]
     unsigned long long *hist;   // [sum bins]
-    unsigned int *acc_log;      // [walkers][acc_log_words] or null
+    unsigned int *acc_log;      // [walkers][acc_log_words] or null: per walker, two words holding
+                                // the walker's single-bead moves when the log was armed (bit i of
+                                // the rest is its i-th move since), then the bits
     long long acc_log_moves;
-    int acc_log_words;
+    int acc_log_words;          // row stride in words (2 + bit words)
     int npad;                   // coordinate stride per axis (64 or 128)
     int *err;                   // device error word (first error code wins)
     double c_lj[kMaxTypes * kMaxTypes];
@@ -75,8 +77,6 @@ struct SweepArgs {
     int resync_sweeps;
     double drift_tol;
     unsigned int seed_lo, seed_hi;
-    const unsigned long long *acc_log_base;  // [walkers] single-bead moves done when the log
-                                             // was armed: bit i is the walker's i-th move since
 };
 
 // ------------------------------------------------------------------------------------------

@@ -53,7 +53,6 @@ struct muca_ctx {
     unsigned long long *d_cnt = nullptr, *d_hist = nullptr, *d_hist_last = nullptr;
     double *d_beta = nullptr, *d_alpha = nullptr, *d_g = nullptr;
     unsigned int *d_acclog = nullptr;
-    unsigned long long *d_acclog_base = nullptr;   // [walkers] moves done when the log was armed
     long long acclog_moves = 0;
     int acclog_words = 0;
     long long *d_iter = nullptr;
@@ -428,7 +427,7 @@ void muca_destroy(muca_ctx *ctx) {
     void *ptrs[] = {ctx->d_sys, ctx->d_work, ctx->d_binfo, ctx->d_err, ctx->d_walker_sys,
                     ctx->d_pos, ctx->d_energy, ctx->d_drift, ctx->d_cnt, ctx->d_hist,
                     ctx->d_hist_last, ctx->d_beta, ctx->d_alpha, ctx->d_g, ctx->d_acclog,
-                    ctx->d_acclog_base, ctx->d_iter, ctx->d_stats, ctx->d_theta_part, ctx->d_hmc};
+                    ctx->d_iter, ctx->d_stats, ctx->d_theta_part, ctx->d_hmc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -654,7 +653,6 @@ int muca_init(const muca_config *cfg, muca_ctx **out) {
     a.alpha = ctx->d_alpha;
     a.hist = ctx->d_hist;
     a.acc_log = nullptr;
-    a.acc_log_base = nullptr;
     a.acc_log_moves = 0;
     a.acc_log_words = 0;
     a.npad = ctx->npad;
@@ -942,25 +940,26 @@ int muca_set_accept_log(muca_ctx *ctx, int64_t n_moves) {
     if (n_moves < 0) return fail(ctx, MUCA_E_INVAL, "negative log length");
     CK(hipStreamSynchronize(ctx->stream));
     if (ctx->d_acclog) { CK(hipFree(ctx->d_acclog)); ctx->d_acclog = nullptr; }
-    if (ctx->d_acclog_base) { CK(hipFree(ctx->d_acclog_base)); ctx->d_acclog_base = nullptr; }
     ctx->acclog_moves = n_moves;
-    ctx->acclog_words = (int)((n_moves + 31) / 32);
+    // per walker: two header words (its move counter now: the log counts moves from here on,
+    // over any number of calls and launches), then the bits
+    ctx->acclog_words = 2 + (int)((n_moves + 31) / 32);
     if (n_moves > 0) {
-        const size_t bytes = sizeof(unsigned int) * (size_t)ctx->acclog_words * ctx->W_total;
-        CK(hipMalloc(&ctx->d_acclog, bytes));
-        std::vector<unsigned int> z((size_t)ctx->acclog_words * ctx->W_total, 0u);
-        CK(hipMemcpy(ctx->d_acclog, z.data(), bytes, hipMemcpyHostToDevice));
-        // the log counts moves from now on, over any number of calls and launches
-        std::vector<unsigned long long> c((size_t)ctx->W_total * C_NCOUNT), base(ctx->W_total);
+        const size_t words = (size_t)ctx->acclog_words * ctx->W_total;
+        std::vector<unsigned long long> c((size_t)ctx->W_total * C_NCOUNT);
         CK(hipMemcpy(c.data(), ctx->d_cnt, sizeof(unsigned long long) * c.size(),
                      hipMemcpyDeviceToHost));
-        for (int w = 0; w < ctx->W_total; ++w) base[w] = c[(size_t)w * C_NCOUNT + C_MOVES];
-        CK(hipMalloc(&ctx->d_acclog_base, sizeof(unsigned long long) * base.size()));
-        CK(hipMemcpy(ctx->d_acclog_base, base.data(), sizeof(unsigned long long) * base.size(),
+        std::vector<unsigned int> rows(words, 0u);
+        for (int w = 0; w < ctx->W_total; ++w) {
+            const unsigned long long base = c[(size_t)w * C_NCOUNT + C_MOVES];
+            rows[(size_t)w * ctx->acclog_words] = (unsigned int)base;
+            rows[(size_t)w * ctx->acclog_words + 1] = (unsigned int)(base >> 32);
+        }
+        CK(hipMalloc(&ctx->d_acclog, sizeof(unsigned int) * words));
+        CK(hipMemcpy(ctx->d_acclog, rows.data(), sizeof(unsigned int) * words,
                      hipMemcpyHostToDevice));
     }
     ctx->args.acc_log = ctx->d_acclog;
-    ctx->args.acc_log_base = ctx->d_acclog_base;
     ctx->args.acc_log_moves = n_moves;
     ctx->args.acc_log_words = ctx->acclog_words;
     drop_graphs(ctx);
@@ -979,7 +978,7 @@ int muca_get_accept_log(muca_ctx *ctx, int32_t sys, uint8_t *out, int64_t n_move
                  sizeof(unsigned int) * bits.size(), hipMemcpyDeviceToHost));
     for (int w = 0; w < W; ++w)
         for (int64_t m = 0; m < n_moves; ++m)
-            out[(size_t)w * n_moves + m] = (bits[(size_t)w * nw + (m >> 5)] >> (m & 31)) & 1u;
+            out[(size_t)w * n_moves + m] = (bits[(size_t)w * nw + 2 + (m >> 5)] >> (m & 31)) & 1u;
     return MUCA_OK;
 }
 

@@ -302,8 +302,9 @@ __device__ void run_walker(const SweepArgs &a, const SysDev &sd, int sys, int w,
             n_wrej += inwin ? 0u : 1u;
             if (alog && accept && lane == 0) {
                 // moves since the log was armed (the counter is written back at the launch end)
-                const long long li = (long long)(cnt[C_MOVES] - a.acc_log_base[w]) + n_mv;
-                if (li >= 0 && li < a.acc_log_moves) atomicOr(&alog[li >> 5], 1u << (li & 31));
+                const unsigned long long base = ((unsigned long long)alog[1] << 32) | alog[0];
+                const long long li = (long long)(cnt[C_MOVES] - base) + n_mv;
+                if (li >= 0 && li < a.acc_log_moves) atomicOr(&alog[2 + (li >> 5)], 1u << (li & 31));
             }
             ++n_mv;
             if (accept) {

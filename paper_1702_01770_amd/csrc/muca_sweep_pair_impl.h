@@ -76,7 +76,10 @@ __device__ __forceinline__ double half_sum_d(double v) {
     return row_pair_sum(v);
 }
 // FP32 row sums, combined in FP64 (the 64-bit swap pattern above; the compiler folds the two
-// results of a 32-bit swap of one value into one).
+// results of a 32-bit swap of one value into one).  Adding the row sums in FP32 instead saves two
+// instructions but adds a rounding of the size of the largest row sum to every move; with the
+// large, cancelling pair terms of overlapping beads that took the running-energy drift of 100
+// flat-weight sweeps past 1e-3.
 __device__ __forceinline__ double half_sum_f(float v) {
     v += dpp_f<0xB1>(v);
     v += dpp_f<0x4E>(v);
@@ -409,16 +412,17 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                     dyn = min_img(dyn, a.box_len, a.inv_box);
                     dzn = min_img(dzn, a.box_len, a.inv_box);
                 }
-                const A fxo = (A)dxo, fyo = (A)dyo, fzo = (A)dzo;
-                const A fxn = (A)dxn, fyn = (A)dyn, fzn = (A)dzn;
-                // unused lanes (r2 may be 0 there) are dropped by the select below
-                const A r2o = fxo * fxo + fyo * fyo + fzo * fzo;
-                const A r2n = fxn * fxn + fyn * fyn + fzn * fzn;
+                // r^2 in FP64 (the FP64 fused multiply-add issues at the FP32 rate, and one
+                // conversion of r^2 replaces three of the components), the rest in A; unused lanes
+                // (r2 may be 0 there) are dropped by the select below
+                const double r2o = dxo * dxo + dyo * dyo + dzo * dzo;
+                const double r2n = dxn * dxn + dyn * dyn + dzn * dzn;
                 A so, sn2;
                 if constexpr (FP64) {
                     so = 1.0 / r2o; sn2 = 1.0 / r2n;
                 } else {
-                    so = __builtin_amdgcn_rcpf(r2o); sn2 = __builtin_amdgcn_rcpf(r2n);
+                    so = __builtin_amdgcn_rcpf((float)r2o);
+                    sn2 = __builtin_amdgcn_rcpf((float)r2n);
                 }
                 const A s3o = so * so * so, s3n = sn2 * sn2 * sn2;
                 const A t = s3n * (kk[s].x * s3n - kk[s].y) - s3o * (kk[s].x * s3o - kk[s].y);
@@ -441,8 +445,9 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 // bit of this move: moves since the log was armed (the walker's move counter is
                 // written back only at the end of the launch); the offset is read here, in the
                 // logging path only, so that no extra state stays live in the move loop
-                const long long li = (long long)(cnt[C_MOVES] - a.acc_log_base[w]) + n_mv;
-                if (li >= 0 && li < a.acc_log_moves) atomicOr(&alog[li >> 5], 1u << (li & 31));
+                const unsigned long long base = ((unsigned long long)alog[1] << 32) | alog[0];
+                const long long li = (long long)(cnt[C_MOVES] - base) + n_mv;
+                if (li >= 0 && li < a.acc_log_moves) atomicOr(&alog[2 + (li >> 5)], 1u << (li & 31));
             }
             ++n_mv;
             if (accept) {
