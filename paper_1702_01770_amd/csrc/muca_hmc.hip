@@ -220,17 +220,26 @@ __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs 
     const double hs = h.step;
 
     for (long long tr = 0; tr < h.n_traj; ++tr, ++T) {
+        // Per-trajectory copies of the lane index and the row pointer, opaque to the compiler
+        // (empty asm statements that only tie a register), so that it recomputes the lane's row
+        // addresses and the first Philox round of the momentum counter here instead of hoisting
+        // them out of the trajectory loop, where they held registers through the force
+        // evaluations and were spilled to scratch.
+        int lane_t = lane;
+        double *Pt = P;
+        asm volatile("" : "+v"(lane_t));
+        asm volatile("" : "+s"(Pt));
         // the walker's state stays in its position rows (rewritten on acceptance), read once per
         // trajectory, so that no register holds it across the force evaluations
-        const double x = act ? P[lane] : 0.0, y = act ? P[a.npad + lane] : 0.0,
-                     z = act ? P[2 * a.npad + lane] : 0.0;
+        const double x = act ? Pt[lane_t] : 0.0, y = act ? Pt[a.npad + lane_t] : 0.0,
+                     z = act ? Pt[2 * a.npad + lane_t] : 0.0;
         L.x[lane] = x; L.y[lane] = y; L.z[lane] = z;
         __builtin_amdgcn_wave_barrier();
         // vectors: the first bead's position, else the bond ending at this bead
         double vx = x, vy = y, vz = z;
         if (act && !first) { vx = x - L.x[lane - 1]; vy = y - L.y[lane - 1]; vz = z - L.z[lane - 1]; }
         // momenta
-        const U4 r = philox4x32_10((unsigned)lane, (unsigned)T, (unsigned)(T >> 32), 7u, k0, k1);
+        const U4 r = philox4x32_10((unsigned)lane_t, (unsigned)T, (unsigned)(T >> 32), 7u, k0, k1);
         const double a0 = u01(r.x), a1 = u01(r.y), a2 = u01(r.z), a3 = u01(r.w);
         const double r0 = sqrt(-2.0 * log(a0)), r2 = sqrt(-2.0 * log(a2));
         double mx = r0 * cos(2.0 * M_PI * a1), my = r0 * sin(2.0 * M_PI * a1), mz = r2 * cos(2.0 * M_PI * a3);
@@ -305,7 +314,7 @@ __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs 
         const bool accept = inwin && inside && (log(u01(ra.x)) < H0 - H1);
         n_wrej += inwin ? 0 : 1;
         if (accept) {
-            if (act) { P[lane] = nx; P[a.npad + lane] = ny; P[2 * a.npad + lane] = nz; }
+            if (act) { Pt[lane_t] = nx; Pt[a.npad + lane_t] = ny; Pt[2 * a.npad + lane_t] = nz; }
             E = Ec;
             ++n_acc;
         } else {
