@@ -716,8 +716,9 @@ def main():
     ap.add_argument("--sweeps", type=int, default=100000, help="sweeps per MUCA iteration")
     ap.add_argument("--skip", default="", help="comma-separated legs to skip: " + ",".join(LEGS))
     ap.add_argument("--only", default="",
-                    help="run only this leg (main, matched, c3, c4, c2_fp64, pivots, paper, hmc, "
-                         "diff, cpu) and print it alone (profiling)")
+                    help="run only this leg (main, matched, c3, c4, c2_fp64, "
+                         "c2_fp32_same_schedule, pivots, paper, hmc, diff, cpu) and print it "
+                         "alone (profiling)")
     ap.add_argument("--paper-physics", default="",
                     help="comma-separated paper systems: only run their full MUCA + analysis")
     ap.add_argument("--physics-iters", type=int, default=1000)
@@ -756,6 +757,11 @@ def main():
                                  1, st),
         "c2_fp64": lambda: config_leg("batched single chains (the headline workload) in FP64",
                                       wl, 20000, 3, 1, st, precision=0),
+        # the same schedule in the FP32-split mode: the FP64 line's counterpart at the same
+        # weights' history and hence acceptance (the headline runs longer iterations)
+        "c2_fp32_same_schedule": lambda: config_leg(
+            "batched single chains (the headline workload), FP32-split, on the FP64 line's "
+            "schedule", wl, 20000, 3, 1, st),
     }
     single = dict(configs, matched=lambda: matched_error(st),
                   pivots=lambda: chain_moves_leg(wl, st), paper=lambda: paper_systems_leg(st),
