@@ -135,6 +135,11 @@ __device__ __forceinline__ double lnw_at(const double *le, int k, double t) {
     const double l0 = le[k], l1 = le[k + 1];
     return l0 + (l1 - l0) * (t - (double)k);
 }
+// The same for t inside the window, k = floor(t): t - k is the fractional part of t (exact).
+__device__ __forceinline__ double lnw_in(const double *le, int k, double t) {
+    const double l0 = le[k], l1 = le[k + 1];
+    return l0 + (l1 - l0) * __builtin_amdgcn_fract(t);
+}
 
 // v -> R v for the rotation by the angle with cosine co and sine sn about the unit axis k
 // (Rodrigues' formula).
@@ -166,6 +171,16 @@ struct Staged {
 // Entries of the bending / torsion coefficient table (4 variants of 8).
 constexpr int kAngcEntries = 32;
 
+// Bead key j + 256 c of bead j in chain c: keys of beads in different chains differ by more than
+// 128, so "the same chain and within d beads" is one comparison of key differences for d < 128.
+__device__ __forceinline__ int bead_key(int j, int inf) { return j + 256 * bi_chain(inf); }
+
+// Per-move values of the moved bead b, staged with the draws: its key, its descriptor and its
+// bonded neighbours (b itself in place of a missing one at a chain end).
+struct StagedBead {
+    int key, inf, bm, bp;
+};
+
 struct PairLds {
     const double *lw;          // ln W at the K + 1 bin edges of this walker's system
     unsigned int *hist;        // LDS histogram of this walker's system
@@ -174,7 +189,7 @@ struct PairLds {
     const double *ctab;        // C_LJ[t][u], t, u < kMaxTypes
     const void *kc;            // {kappa, kappa C_LJ}[intra / inter][t][u] in the accumulator type
     const void *angc;          // bending / torsion coefficients of u_j . m, [first + 2 last][j - b + 3]
-    int2 *sb;                  // staged bead index and descriptor of the next G moves (+1 spare)
+    StagedBead *sb;            // staged moved beads of the next G moves (+1 spare)
     Staged *sq;                // staged random values of the next G moves (+1 spare)
 };
 
@@ -265,7 +280,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
     // lane state: bond to the next bead of the chain (accumulator type), descriptor, chain and
     // row offset into the coupling table; the coordinates themselves live in the LDS mirror only
     A ux[SLOTS], uy[SLOTS], uz[SLOTS];
-    int inf[SLOTS], chn[SLOTS], trow[SLOTS];
+    int inf[SLOTS], chn[SLOTS], trow[SLOTS], kp1[SLOTS], kb1[SLOTS];
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const int j = gl + G * s;
@@ -273,6 +288,10 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
         inf[s] = alive ? L.binfo[j] : bead_info(0, 255, true, true);
         chn[s] = bi_chain(inf[s]);
         trow[s] = bi_type(inf[s]) * kMaxTypes;
+        // bead key + 1 (far from every key in empty lanes); the same for the lane's bond to the
+        // next bead, far from every key where there is none
+        kp1[s] = alive ? bead_key(j, inf[s]) + 1 : 0x40000000;
+        kb1[s] = alive && !bi_last(inf[s]) ? kp1[s] : 0x40000000;
         if (alive && !bi_last(inf[s])) {
             ux[s] = (A)(L.x[j + 1] - L.x[j]);
             uy[s] = (A)(L.y[j + 1] - L.y[j]);
@@ -315,8 +334,9 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             const double u1 = u01(r.y), u2 = u01(r.z), u3 = u01(r.w);
             // end bead: g uniform on the sphere; interior bead: rotation cosine / sine
             const int binf_l = L.binfo[blane];
+            const bool fs = bi_first(binf_l), ls = bi_last(binf_l);
             Staged q;
-            if (bi_first(binf_l) || bi_last(binf_l)) {
+            if (fs || ls) {
                 const double zc = 2.0 * u1 - 1.0;
                 double spsi, cpsi;
                 sincos(2.0 * M_PI * u2, &spsi, &cpsi);
@@ -327,21 +347,25 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 q.q2 = 0.0;
             }
             q.lnu = log(u3);
-            L.sb[gl] = make_int2(blane, binf_l);
+            L.sb[gl] = StagedBead{bead_key(blane, binf_l), binf_l, fs ? blane : blane - 1,
+                                  ls ? blane : blane + 1};
             L.sq[gl] = q;
-            if (gl == 0) L.sb[G] = make_int2(0, L.binfo[0]);    // spare entry for the last prefetch
+            if (gl == 0) {                          // spare entry for the last prefetch
+                const int i0 = L.binfo[0];
+                L.sb[G] = StagedBead{bead_key(0, i0), i0, 0, 0};
+            }
             __builtin_amdgcn_wave_barrier();
         }
-        int2 bi_nx = L.sb[0];
+        StagedBead bi_nx = L.sb[0];
 
         for (int i = 0; i < nblk; ++i) {
             // everything read here depends only on the staged draw of this move, so all of it is
             // in flight at once; the draw of the next move is read now as well
             // the proposal's inputs (neighbours, moved bead, draws) are requested first, the
             // pair loop's (this lane's beads, couplings) behind them
-            const int b = bi_nx.x, infb = bi_nx.y;
+            const int bkey = bi_nx.key, infb = bi_nx.inf, bm = bi_nx.bm, bp = bi_nx.bp;
+            const int b = bkey & 0xff;
             const bool fst = bi_first(infb), lst = bi_last(infb);
-            const int bm = fst ? b : b - 1, bp = lst ? b : b + 1;
             const double xmx = L.x[bm], xmy = L.y[bm], xmz = L.z[bm];
             const double xpx = L.x[bp], xpy = L.y[bp], xpz = L.z[bp];
             const double xbx = L.x[b], xby = L.y[b], xbz = L.z[b];
@@ -350,7 +374,8 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             const int tb = bi_type(infb), cb = bi_chain(infb);
             // coupling of every slot's bead with b, and the coefficient of u_j . m for
             // j = b-3 .. b+2 of the same chain (0 elsewhere: entry 6)
-            const A *act = reinterpret_cast<const A *>(L.angc) + (fst ? 8 : 0) + (lst ? 16 : 0);
+            // (first ? 8 : 0) + (last ? 16 : 0) from descriptor bits 16 and 17
+            const A *act = reinterpret_cast<const A *>(L.angc) + ((infb >> 13) & 0x18);
             A2 kk[SLOTS];
             A coef[SLOTS];
             double px[SLOTS], py[SLOTS], pz[SLOTS];
@@ -359,8 +384,8 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             for (int s = 0; s < SLOTS; ++s) {
                 const bool same = chn[s] == cb;
                 kk[s] = kct[(same ? 0 : kMaxTypes * kMaxTypes) + trow[s] + tb];
-                const unsigned ai = min((unsigned)(gl + G * s - b + 3), 6u);
-                coef[s] = act[same ? ai : 6u];
+                // entry j - b + 3 for j = b-3 .. b+2 of b's chain, 6 (zero) for every other bead
+                coef[s] = act[min((unsigned)(kp1[s] - bkey + 2), 6u)];
             }
             double nx, ny, nz;
             if (fst || lst) {
@@ -379,11 +404,10 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 const double kx = ax * ra, ky = ay * ra, kz = az * ra;
                 const double vx = xbx - xmx, vy = xby - xmy, vz = xbz - xmz;
                 const double cx = ky * vz - kz * vy, cy = kz * vx - kx * vz, cz = kx * vy - ky * vx;
-                const double kv = kx * vx + ky * vy + kz * vz;
-                const double omc = 1.0 - c;
-                nx = xmx + (vx * c + cx * sn + kx * kv * omc);
-                ny = xmy + (vy * c + cy * sn + ky * kv * omc);
-                nz = xmz + (vz * c + cz * sn + kz * kv * omc);
+                const double kvo = (kx * vx + ky * vy + kz * vz) * (1.0 - c);
+                nx = xmx + (vx * c + cx * sn + kx * kvo);
+                ny = xmy + (vy * c + cy * sn + ky * kvo);
+                nz = xmz + (vz * c + cz * sn + kz * kvo);
             }
             // bond b-1 changes by -m, bond b by +m (m = x'_b - x_b): every other bending or
             // torsion term that uses one of them changes by a multiple of u_j . m
@@ -394,11 +418,9 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             for (int s = 0; s < SLOTS; ++s) {
                 if (s > 0 && G * s >= N) break;          // wave-uniform: no bead in this slot
                 const int j = gl + G * s;
-                const int d = j - b;
-                const bool same = chn[s] == cb;
-                // skip the moved bead itself (d = 0, same chain), its bonded neighbours and empty
+                // skip the moved bead itself, its bonded neighbours (keys within 1) and empty
                 // lanes
-                const bool use = (j < N) && !(same && (unsigned)(d + 1) <= 2u);
+                const bool use = (j < N) && (unsigned)(kp1[s] - bkey) > 2u;
                 // both separations from the FP64 coordinates, each rounded once: taking the new
                 // one as (old - m) in FP32 would carry the rounding of m into every pair at once
                 // (a coherent error F . dm per move that doubled the running-energy drift)
@@ -426,7 +448,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 }
                 const A s3o = so * so * so, s3n = sn2 * sn2 * sn2;
                 const A t = s3n * (kk[s].x * s3n - kk[s].y) - s3o * (kk[s].x * s3o - kk[s].y);
-                acc += use ? t : (A)0;
+                acc = s == 0 ? (use ? t : (A)0) : acc + (use ? t : (A)0);
                 acc += coef[s] * (ux[s] * mxa + uy[s] * mya + uz[s] * mza);
             }
             const double dE = group_sum<G>(acc);
@@ -434,30 +456,35 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             const double t = bin_coord(En, e_lo, a.bin_width, inv_eps);
             const bool inwin = (t >= 0.0) && (t < (double)K);
             const int kn = inwin ? (int)t : 0;
-            const double lnw_new = lnw_at(L.lw, kn, t);
+            const double lnw_new = lnw_in(L.lw, kn, t);   // used only inside the window
             // steric sphere: a bead may not leave it
             bool inside = true;
             if (__builtin_expect(a.sphere_r2 > 0.0, 0))
                 inside = nx * nx + ny * ny + nz * nz <= a.sphere_r2;
             const bool accept = inwin && inside && (q.lnu < lnw_new - lnw_cur);
             n_wrej += inwin ? 0u : 1u;
-            if (alog && accept && gl == 0) {
-                // bit of this move: moves since the log was armed (the walker's move counter is
-                // written back only at the end of the launch); the offset is read here, in the
-                // logging path only, so that no extra state stays live in the move loop
-                const unsigned long long base = ((unsigned long long)alog[1] << 32) | alog[0];
-                const long long li = (long long)(cnt[C_MOVES] - base) + n_mv;
-                if (li >= 0 && li < a.acc_log_moves) atomicOr(&alog[2 + (li >> 5)], 1u << (li & 31));
+            if (a.acc_log != nullptr) {             // wave-uniform: armed for the whole launch
+                if (accept && gl == 0) {
+                    // bit of this move: moves since the log was armed (the walker's move counter
+                    // is written back only at the end of the launch); the offset is read here, in
+                    // the logging path only, so that no extra state stays live in the move loop
+                    const unsigned long long base = ((unsigned long long)alog[1] << 32) | alog[0];
+                    const long long li = (long long)(cnt[C_MOVES] - base) + n_mv;
+                    if (li >= 0 && li < a.acc_log_moves)
+                        atomicOr(&alog[2 + (li >> 5)], 1u << (li & 31));
+                }
             }
             ++n_mv;
             if (accept) {
-                // bonds b-1 and b recomputed from the coordinates (no accumulated rounding)
-                const A bmx = (A)(nx - xmx), bmy = (A)(ny - xmy), bmz = (A)(nz - xmz);
-                const A bpx = (A)(xpx - nx), bpy = (A)(xpy - ny), bpz = (A)(xpz - nz);
+                // bonds b-1 and b recomputed from the coordinates (no accumulated rounding),
+                // converted once and then selected by the lanes that hold them
+                A bmx = (A)(nx - xmx), bmy = (A)(ny - xmy), bmz = (A)(nz - xmz);
+                A bpx = (A)(xpx - nx), bpy = (A)(xpy - ny), bpz = (A)(xpz - nz);
+                asm volatile("" : "+v"(bmx), "+v"(bmy), "+v"(bmz), "+v"(bpx), "+v"(bpy), "+v"(bpz));
 #pragma unroll
                 for (int s = 0; s < SLOTS; ++s) {
-                    const int j = gl + G * s;
-                    const bool lo_b = (j == b - 1) && !fst, at_b = (j == b) && !lst;
+                    // the lane's bond ends at b (bond b-1) or starts at b (bond b)
+                    const bool lo_b = kb1[s] == bkey, at_b = kb1[s] == bkey + 1;
                     ux[s] = lo_b ? bmx : (at_b ? bpx : ux[s]);
                     uy[s] = lo_b ? bmy : (at_b ? bpy : uy[s]);
                     uz[s] = lo_b ? bmz : (at_b ? bpz : uz[s]);
@@ -855,7 +882,7 @@ struct PairShared {
     const int *binfo;
     double *coord;           // wave slabs of kSlabCoord doubles
     Staged *sq;              // wave slabs of kSlabStage entries
-    int2 *sb;
+    StagedBead *sb;
     int slab_coord, slab_stage;
 };
 
@@ -886,11 +913,11 @@ __device__ void pair_wave(const SweepArgs &a, const WorkItem &wi, int wave, cons
 }
 
 // LDS layout (per workgroup), 16-byte items first: the {kappa, kappa C_LJ} table (intra, inter)
-// in the accumulator type; the bending / torsion coefficient table; the staged draws (one slab
-// per wave); the C_LJ table; the coordinate mirrors (one slab per wave); ln W at the bin edges of
-// every system of the workgroup (system i at lds_off[i] + i); the staged bead indices and
-// descriptors (one slab per wave); the 32-bit histograms (system i at lds_off[i]); the bead
-// descriptors of every system.
+// in the accumulator type; the bending / torsion coefficient table; the staged draws and the
+// staged moved beads (one slab each per wave); the C_LJ table; the coordinate mirrors (one slab
+// per wave); ln W at the bin edges of every system of the workgroup (system i at
+// lds_off[i] + i); the 32-bit histograms (system i at lds_off[i]); the bead descriptors of every
+// system.
 // G > 0: every wave holds 64 / G walkers in groups of G lanes with SLOTS bead slots per lane.
 // G = 0 (mixed plan): wave v holds walkers of lanes-per-walker wi.kind[v], with the slots fixed
 // per kind (16 lanes: 2 slots, at most 32 beads; 32 lanes: 2 slots; 64 lanes: 1 slot), so long
@@ -909,11 +936,11 @@ __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_swe
     A2 *kc = reinterpret_cast<A2 *>(lds_p);
     A *angc = reinterpret_cast<A *>(lds_p + 2 * kMaxTypes * kMaxTypes);
     Staged *sq = reinterpret_cast<Staged *>(lds_p + 2 * kMaxTypes * kMaxTypes + kAngcEntries / 2);
-    double *ctab = reinterpret_cast<double *>(sq + (size_t)n_waves * kSlabStage);
+    StagedBead *sb = reinterpret_cast<StagedBead *>(sq + (size_t)n_waves * kSlabStage);
+    double *ctab = reinterpret_cast<double *>(sb + (size_t)n_waves * kSlabStage);
     double *pc = ctab + kMaxTypes * kMaxTypes;
     double *lw = pc + (size_t)n_waves * kSlabCoord;
-    int2 *sb = reinterpret_cast<int2 *>(lw + bins_total + ns);
-    unsigned int *hist = reinterpret_cast<unsigned int *>(sb + (size_t)n_waves * kSlabStage);
+    unsigned int *hist = reinterpret_cast<unsigned int *>(lw + bins_total + ns);
     int *binfo = reinterpret_cast<int *>(hist + bins_total);
     for (int i = 0; i < ns; ++i) {
         const SysDev &sd = a.sys[wi.sys[i]];
