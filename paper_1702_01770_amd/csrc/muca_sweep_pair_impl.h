@@ -141,6 +141,15 @@ __device__ __forceinline__ double lnw_in(const double *le, int k, double t) {
     return l0 + (l1 - l0) * __builtin_amdgcn_fract(t);
 }
 
+// 1 / sqrt(x) for finite x > 0: the hardware estimate r refined by the second-order step
+// r (1 + e/2 + 3 e^2 / 8), e = 1 - x r^2 (the terms of (1 - e)^(-1/2)); no special-value handling
+// (x = 0 gives NaN instead of inf, which the callers treat alike: the move is rejected).
+__device__ __forceinline__ double rsqrt_pos(double x) {
+    const double r = __builtin_amdgcn_rsq(x);
+    const double e = fma(r * -x, r, 1.0);
+    return fma(r * e, fma(e, 0.375, 0.5), r);
+}
+
 // v -> R v for the rotation by the angle with cosine co and sine sn about the unit axis k
 // (Rodrigues' formula).
 __device__ __forceinline__ void rot3(double kx, double ky, double kz, double co, double sn,
@@ -262,7 +271,9 @@ __device__ double full_energy_pair(const SweepArgs &a, int N, const PairLds &L,
     return group_sum<G>(acc);
 }
 
-template <bool FP64, int G, int SLOTS, bool PERIODIC, bool CHAIN>
+// LOG: the accept log is armed (a separate instance, so that the move loop of the ordinary one
+// carries no logging test).
+template <bool FP64, int G, int SLOTS, bool PERIODIC, bool CHAIN, bool LOG>
 __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const PairLds &L,
                          long long n_sweeps) {
     using A = AccP<FP64>;
@@ -319,7 +330,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
     const long long total = n_sweeps * (long long)N;
     long long done = 0;
     int m = 0;
-    unsigned int *alog = a.acc_log ? a.acc_log + (size_t)w * a.acc_log_words : nullptr;
+    unsigned int *alog = LOG && a.acc_log ? a.acc_log + (size_t)w * a.acc_log_words : nullptr;
 
     while (done < total) {
         // ---- each group draws the next (up to) G moves of its walker, one per lane ----
@@ -365,7 +376,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             // pair loop's (this lane's beads, couplings) behind them
             const int bkey = bi_nx.key, infb = bi_nx.inf, bm = bi_nx.bm, bp = bi_nx.bp;
             const int b = bkey & 0xff;
-            const bool fst = bi_first(infb), lst = bi_last(infb);
+            const bool fst = bi_first(infb);
             const double xmx = L.x[bm], xmy = L.y[bm], xmz = L.z[bm];
             const double xpx = L.x[bp], xpy = L.y[bp], xpz = L.z[bp];
             const double xbx = L.x[b], xby = L.y[b], xbz = L.z[b];
@@ -388,19 +399,19 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 coef[s] = act[min((unsigned)(kp1[s] - bkey + 2), 6u)];
             }
             double nx, ny, nz;
-            if (fst || lst) {
+            if ((unsigned)infb > 0xffffu) {         // first or last bead (descriptor bits 16, 17)
                 // end bead: new bond along (x_b - x_a) + rho g, unit length, from anchor a
                 const double xax = fst ? xpx : xmx, xay = fst ? xpy : xmy, xaz = fst ? xpz : xmz;
                 const double vx = (xbx - xax) + a.cap_rho * q.q0;
                 const double vy = (xby - xay) + a.cap_rho * q.q1;
                 const double vz = (xbz - xaz) + a.cap_rho * q.q2;
-                const double rv = rsqrt(vx * vx + vy * vy + vz * vz);
+                const double rv = rsqrt_pos(vx * vx + vy * vy + vz * vz);
                 nx = xax + vx * rv; ny = xay + vy * rv; nz = xaz + vz * rv;
             } else {
                 // crankshaft: rotate x_b about the axis x_{b-1} -> x_{b+1} (Rodrigues)
                 const double c = q.q0, sn = q.q1;
                 const double ax = xpx - xmx, ay = xpy - xmy, az = xpz - xmz;
-                const double ra = rsqrt(ax * ax + ay * ay + az * az);
+                const double ra = rsqrt_pos(ax * ax + ay * ay + az * az);
                 const double kx = ax * ra, ky = ay * ra, kz = az * ra;
                 const double vx = xbx - xmx, vy = xby - xmy, vz = xbz - xmz;
                 const double cx = ky * vz - kz * vy, cy = kz * vx - kx * vz, cz = kx * vy - ky * vx;
@@ -458,12 +469,12 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             const int kn = inwin ? (int)t : 0;
             const double lnw_new = lnw_in(L.lw, kn, t);   // used only inside the window
             // steric sphere: a bead may not leave it
-            bool inside = true;
+            bool accept = inwin && (q.lnu < lnw_new - lnw_cur);
+            // steric sphere: a bead may not leave it (the test is uniform over the launch)
             if (__builtin_expect(a.sphere_r2 > 0.0, 0))
-                inside = nx * nx + ny * ny + nz * nz <= a.sphere_r2;
-            const bool accept = inwin && inside && (q.lnu < lnw_new - lnw_cur);
+                accept = accept && nx * nx + ny * ny + nz * nz <= a.sphere_r2;
             n_wrej += inwin ? 0u : 1u;
-            if (a.acc_log != nullptr) {             // wave-uniform: armed for the whole launch
+            if (LOG && alog != nullptr) {
                 if (accept && gl == 0) {
                     // bit of this move: moves since the log was armed (the walker's move counter
                     // is written back only at the end of the launch); the offset is read here, in
@@ -909,7 +920,15 @@ __device__ void pair_wave(const SweepArgs &a, const WorkItem &wi, int wave, cons
     L.angc = sh.angc;
     L.sb = sh.sb + (size_t)wave * sh.slab_stage + grp * kStage;
     L.sq = sh.sq + (size_t)wave * sh.slab_stage + grp * kStage;
-    run_pair<FP64, G, SLOTS, PERIODIC, CHAIN>(a, sd, w0 + grp, L, n_sweeps);
+    // the chain-move instance keeps the logging test in its loop (one instance instead of two)
+    if constexpr (CHAIN) {
+        run_pair<FP64, G, SLOTS, PERIODIC, CHAIN, true>(a, sd, w0 + grp, L, n_sweeps);
+    } else {
+        if (a.acc_log != nullptr)
+            run_pair<FP64, G, SLOTS, PERIODIC, CHAIN, true>(a, sd, w0 + grp, L, n_sweeps);
+        else
+            run_pair<FP64, G, SLOTS, PERIODIC, CHAIN, false>(a, sd, w0 + grp, L, n_sweeps);
+    }
 }
 
 // LDS layout (per workgroup), 16-byte items first: the {kappa, kappa C_LJ} table (intra, inter)
