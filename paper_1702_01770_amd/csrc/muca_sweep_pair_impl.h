@@ -75,8 +75,7 @@ __device__ __forceinline__ double half_sum_d(double v) {
     v += dpp_d<0x140>(v);
     return row_pair_sum(v);
 }
-// FP32 row sums, combined in FP64 (the 64-bit swap pattern above; the compiler folds the two
-// results of a 32-bit swap of one value into one).  Adding the row sums in FP32 instead saves two
+// FP32 row sums, combined in FP64.  Adding the row sums in FP32 instead saves two
 // instructions but adds a rounding of the size of the largest row sum to every move; with the
 // large, cancelling pair terms of overlapping beads that took the running-energy drift of 100
 // flat-weight sweeps past 1e-3.
@@ -85,7 +84,11 @@ __device__ __forceinline__ double half_sum_f(float v) {
     v += dpp_f<0x4E>(v);
     v += dpp_f<0x141>(v);
     v += dpp_f<0x140>(v);
-    return row_pair_sum((double)v);
+    // the swap on the FP32 row sums, each converted (exactly) before the FP64 add
+    const unsigned u = __builtin_bit_cast(unsigned, v);
+    const auto sw = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    return (double)__builtin_bit_cast(float, (unsigned)sw[0]) +
+           (double)__builtin_bit_cast(float, (unsigned)sw[1]);
 }
 // Sum of the two 32-lane halves of the wave, returned to every lane (gfx950's half swap, with
 // the 64-bit pattern of row_pair_sum).
@@ -408,17 +411,19 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 const double rv = rsqrt_pos(vx * vx + vy * vy + vz * vz);
                 nx = xax + vx * rv; ny = xay + vy * rv; nz = xaz + vz * rv;
             } else {
-                // crankshaft: rotate x_b about the axis x_{b-1} -> x_{b+1} (Rodrigues)
-                const double c = q.q0, sn = q.q1;
+                // crankshaft: rotate x_b about the axis a = x_{b+1} - x_{b-1}.  x_b is at unit
+                // distance from both ends, so w = x_b - h (h the midpoint of the axis) is
+                // perpendicular to a and turns in its plane: x_b' = h + w cos + (a x w) sin / |a|
+                // (Rodrigues' formula without its axial term, which vanishes here)
+                const double c = q.q0;
                 const double ax = xpx - xmx, ay = xpy - xmy, az = xpz - xmz;
-                const double ra = rsqrt_pos(ax * ax + ay * ay + az * az);
-                const double kx = ax * ra, ky = ay * ra, kz = az * ra;
-                const double vx = xbx - xmx, vy = xby - xmy, vz = xbz - xmz;
-                const double cx = ky * vz - kz * vy, cy = kz * vx - kx * vz, cz = kx * vy - ky * vx;
-                const double kvo = (kx * vx + ky * vy + kz * vz) * (1.0 - c);
-                nx = xmx + (vx * c + cx * sn + kx * kvo);
-                ny = xmy + (vy * c + cy * sn + ky * kvo);
-                nz = xmz + (vz * c + cz * sn + kz * kvo);
+                const double sa = q.q1 * rsqrt_pos(ax * ax + ay * ay + az * az);
+                const double hx = fma(0.5, ax, xmx), hy = fma(0.5, ay, xmy), hz = fma(0.5, az, xmz);
+                const double wx = xbx - hx, wy = xby - hy, wz = xbz - hz;
+                const double cx = ay * wz - az * wy, cy = az * wx - ax * wz, cz = ax * wy - ay * wx;
+                nx = fma(cx, sa, fma(wx, c, hx));
+                ny = fma(cy, sa, fma(wy, c, hy));
+                nz = fma(cz, sa, fma(wz, c, hz));
             }
             // bond b-1 changes by -m, bond b by +m (m = x'_b - x_b): every other bending or
             // torsion term that uses one of them changes by a multiple of u_j . m
