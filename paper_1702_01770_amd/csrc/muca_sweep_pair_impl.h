@@ -187,7 +187,8 @@ constexpr int kAngcEntries = 32;
 // 128, so "the same chain and within d beads" is one comparison of key differences for d < 128.
 __device__ __forceinline__ int bead_key(int j, int inf) { return j + 256 * bi_chain(inf); }
 
-// Per-move values of the moved bead b, staged with the draws: its key, its descriptor and its
+// Per-move values of the moved bead b, staged with the draws: its key, its descriptor (with the
+// type byte replaced by the byte offset of the type's column in the coupling table) and its
 // bonded neighbours (b itself in place of a missing one at a chain end).
 struct StagedBead {
     int key, inf, bm, bp;
@@ -274,9 +275,9 @@ __device__ double full_energy_pair(const SweepArgs &a, int N, const PairLds &L,
     return group_sum<G>(acc);
 }
 
-// LOG: the accept log is armed (a separate instance, so that the move loop of the ordinary one
-// carries no logging test).
-template <bool FP64, int G, int SLOTS, bool PERIODIC, bool CHAIN, bool LOG>
+// GEN: the move loop tests for an armed accept log and a steric sphere; the instance without
+// them (GEN = false) carries neither test.
+template <bool FP64, int G, int SLOTS, bool PERIODIC, bool CHAIN, bool GEN>
 __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const PairLds &L,
                          long long n_sweeps) {
     using A = AccP<FP64>;
@@ -333,7 +334,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
     const long long total = n_sweeps * (long long)N;
     long long done = 0;
     int m = 0;
-    unsigned int *alog = LOG && a.acc_log ? a.acc_log + (size_t)w * a.acc_log_words : nullptr;
+    unsigned int *alog = GEN && a.acc_log ? a.acc_log + (size_t)w * a.acc_log_words : nullptr;
 
     while (done < total) {
         // ---- each group draws the next (up to) G moves of its walker, one per lane ----
@@ -361,12 +362,14 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 q.q2 = 0.0;
             }
             q.lnu = log(u3);
-            L.sb[gl] = StagedBead{bead_key(blane, binf_l), binf_l, fs ? blane : blane - 1,
-                                  ls ? blane : blane + 1};
+            L.sb[gl] = StagedBead{bead_key(blane, binf_l),
+                                  (binf_l & ~0xff) | (bi_type(binf_l) * (int)sizeof(A2)),
+                                  fs ? blane : blane - 1, ls ? blane : blane + 1};
             L.sq[gl] = q;
             if (gl == 0) {                          // spare entry for the last prefetch
                 const int i0 = L.binfo[0];
-                L.sb[G] = StagedBead{bead_key(0, i0), i0, 0, 0};
+                L.sb[G] = StagedBead{bead_key(0, i0), (i0 & ~0xff) | (bi_type(i0) * (int)sizeof(A2)),
+                                     0, 0};
             }
             __builtin_amdgcn_wave_barrier();
         }
@@ -385,7 +388,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             const double xbx = L.x[b], xby = L.y[b], xbz = L.z[b];
             const Staged q = L.sq[i];
             bi_nx = L.sb[i + 1];
-            const int tb = bi_type(infb), cb = bi_chain(infb);
+            const int tbo = infb & 0xff, cb = bi_chain(infb);   // b's column, in bytes
             // coupling of every slot's bead with b, and the coefficient of u_j . m for
             // j = b-3 .. b+2 of the same chain (0 elsewhere: entry 6)
             // (first ? 8 : 0) + (last ? 16 : 0) from descriptor bits 16 and 17
@@ -397,7 +400,8 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
 #pragma unroll
             for (int s = 0; s < SLOTS; ++s) {
                 const bool same = chn[s] == cb;
-                kk[s] = kct[(same ? 0 : kMaxTypes * kMaxTypes) + trow[s] + tb];
+                kk[s] = *reinterpret_cast<const A2 *>(
+                    reinterpret_cast<const char *>(kct + (same ? 0 : kMaxTypes * kMaxTypes) + trow[s]) + tbo);
                 // entry j - b + 3 for j = b-3 .. b+2 of b's chain, 6 (zero) for every other bead
                 coef[s] = act[min((unsigned)(kp1[s] - bkey + 2), 6u)];
             }
@@ -476,10 +480,10 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             // steric sphere: a bead may not leave it
             bool accept = inwin && (q.lnu < lnw_new - lnw_cur);
             // steric sphere: a bead may not leave it (the test is uniform over the launch)
-            if (__builtin_expect(a.sphere_r2 > 0.0, 0))
+            if (GEN && a.sphere_r2 > 0.0)
                 accept = accept && nx * nx + ny * ny + nz * nz <= a.sphere_r2;
             n_wrej += inwin ? 0u : 1u;
-            if (LOG && alog != nullptr) {
+            if (GEN && alog != nullptr) {
                 if (accept && gl == 0) {
                     // bit of this move: moves since the log was armed (the walker's move counter
                     // is written back only at the end of the launch); the offset is read here, in
@@ -925,11 +929,11 @@ __device__ void pair_wave(const SweepArgs &a, const WorkItem &wi, int wave, cons
     L.angc = sh.angc;
     L.sb = sh.sb + (size_t)wave * sh.slab_stage + grp * kStage;
     L.sq = sh.sq + (size_t)wave * sh.slab_stage + grp * kStage;
-    // the chain-move instance keeps the logging test in its loop (one instance instead of two)
+    // the chain-move instance keeps both tests in its loop (one instance instead of two)
     if constexpr (CHAIN) {
         run_pair<FP64, G, SLOTS, PERIODIC, CHAIN, true>(a, sd, w0 + grp, L, n_sweeps);
     } else {
-        if (a.acc_log != nullptr)
+        if (a.acc_log != nullptr || a.sphere_r2 > 0.0)
             run_pair<FP64, G, SLOTS, PERIODIC, CHAIN, true>(a, sd, w0 + grp, L, n_sweeps);
         else
             run_pair<FP64, G, SLOTS, PERIODIC, CHAIN, false>(a, sd, w0 + grp, L, n_sweeps);
