@@ -340,9 +340,10 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
         // ---- each group draws the next (up to) G moves of its walker, one per lane ----
         const int nblk = (int)min((long long)G, total - done);
         {
-            const int idx = m + gl;
-            const unsigned long long Sl = S + (unsigned long long)(idx / N);
-            const int ml = idx % N;
+            // idx / N and idx % N by subtraction: idx < N + G, so a few rounds at most
+            int ml = m + gl, qs = 0;
+            while (ml >= N) { ml -= N; ++qs; }
+            const unsigned long long Sl = S + (unsigned long long)qs;
             const U4 r = philox4x32_10((unsigned int)ml, (unsigned int)Sl, (unsigned int)(Sl >> 32),
                                        0u, k0, k1);
             const int blane = (int)(((unsigned long long)r.x * (unsigned long long)N) >> 32);
@@ -350,16 +351,18 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             // end bead: g uniform on the sphere; interior bead: rotation cosine / sine
             const int binf_l = L.binfo[blane];
             const bool fs = bi_first(binf_l), ls = bi_last(binf_l);
+            // one sincos per lane: the azimuth of g for an end bead, the rotation angle for an
+            // interior one (lanes of both kinds share a wave)
+            const bool endb = fs || ls;
+            double sn, cs;
+            sincos(endb ? 2.0 * M_PI * u2 : a.crank_max * (2.0 * u1 - 1.0), &sn, &cs);
             Staged q;
-            if (fs || ls) {
+            if (endb) {
                 const double zc = 2.0 * u1 - 1.0;
-                double spsi, cpsi;
-                sincos(2.0 * M_PI * u2, &spsi, &cpsi);
                 const double sxy = sqrt(fmax(0.0, 1.0 - zc * zc));
-                q.q0 = sxy * cpsi; q.q1 = sxy * spsi; q.q2 = zc;
+                q.q0 = sxy * cs; q.q1 = sxy * sn; q.q2 = zc;
             } else {
-                sincos(a.crank_max * (2.0 * u1 - 1.0), &q.q1, &q.q0);   // q0 = cos, q1 = sin
-                q.q2 = 0.0;
+                q.q0 = cs; q.q1 = sn; q.q2 = 0.0;      // cosine, sine
             }
             q.lnu = log(u3);
             L.sb[gl] = StagedBead{bead_key(blane, binf_l),
