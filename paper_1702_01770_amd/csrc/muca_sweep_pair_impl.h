@@ -480,7 +480,6 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             const bool inwin = (t >= 0.0) && (t < (double)K);
             const int kn = inwin ? (int)t : 0;
             const double lnw_new = lnw_in(L.lw, kn, t);   // used only inside the window
-            // steric sphere: a bead may not leave it
             bool accept = inwin && (q.lnu < lnw_new - lnw_cur);
             // steric sphere: a bead may not leave it (the test is uniform over the launch)
             if (GEN && a.sphere_r2 > 0.0)
