@@ -138,11 +138,6 @@ __device__ __forceinline__ double lnw_at(const double *le, int k, double t) {
     const double l0 = le[k], l1 = le[k + 1];
     return l0 + (l1 - l0) * (t - (double)k);
 }
-// The same for t inside the window, k = floor(t): t - k is the fractional part of t (exact).
-__device__ __forceinline__ double lnw_in(const double *le, int k, double t) {
-    const double l0 = le[k], l1 = le[k + 1];
-    return l0 + (l1 - l0) * __builtin_amdgcn_fract(t);
-}
 
 // 1 / sqrt(x) for finite x > 0: the hardware estimate r refined by the second-order step
 // r (1 + e/2 + 3 e^2 / 8), e = 1 - x r^2 (the terms of (1 - e)^(-1/2)); no special-value handling
@@ -479,7 +474,17 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             const double t = bin_coord(En, e_lo, a.bin_width, inv_eps);
             const bool inwin = (t >= 0.0) && (t < (double)K);
             const int kn = inwin ? (int)t : 0;
-            const double lnw_new = lnw_in(L.lw, kn, t);   // used only inside the window
+            // ln W at the edges of the new bin requested first; the bonds b-1 and b after the
+            // move, recomputed from the coordinates (no accumulated rounding) and converted, are
+            // formed while the read is in flight (the empty asm keeps them ahead of its use)
+            double l0 = L.lw[kn], l1 = L.lw[kn + 1];
+            // t - kn inside the window (the only place ln W is used): the fractional part of t
+            double ft = __builtin_amdgcn_fract(t);
+            A bmx = (A)(nx - xmx), bmy = (A)(ny - xmy), bmz = (A)(nz - xmz);
+            A bpx = (A)(xpx - nx), bpy = (A)(xpy - ny), bpz = (A)(xpz - nz);
+            asm volatile("" : "+v"(bmx), "+v"(bmy), "+v"(bmz), "+v"(bpx), "+v"(bpy), "+v"(bpz),
+                         "+v"(ft), "+v"(l0), "+v"(l1));
+            const double lnw_new = l0 + (l1 - l0) * ft;
             bool accept = inwin && (q.lnu < lnw_new - lnw_cur);
             // steric sphere: a bead may not leave it (the test is uniform over the launch)
             if (GEN && a.sphere_r2 > 0.0)
@@ -498,11 +503,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             }
             ++n_mv;
             if (accept) {
-                // bonds b-1 and b recomputed from the coordinates (no accumulated rounding),
-                // converted once and then selected by the lanes that hold them
-                A bmx = (A)(nx - xmx), bmy = (A)(ny - xmy), bmz = (A)(nz - xmz);
-                A bpx = (A)(xpx - nx), bpy = (A)(xpy - ny), bpz = (A)(xpz - nz);
-                asm volatile("" : "+v"(bmx), "+v"(bmy), "+v"(bmz), "+v"(bpx), "+v"(bpy), "+v"(bpz));
+                // the new bonds selected by the lanes that hold them
 #pragma unroll
                 for (int s = 0; s < SLOTS; ++s) {
                     // the lane's bond ends at b (bond b-1) or starts at b (bond b)
