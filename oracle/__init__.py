@@ -47,7 +47,8 @@ class _System(C.Structure):
 
 class _Weights(C.Structure):
     _fields_ = [("e_lo", C.c_double), ("bin_width", C.c_double), ("n_bins", C.c_int32),
-                ("beta", C.POINTER(C.c_double)), ("alpha", C.POINTER(C.c_double))]
+                ("beta", C.POINTER(C.c_double)), ("alpha", C.POINTER(C.c_double)),
+                ("edge_tol", C.c_double)]
 
 
 class _Moves(C.Structure):
@@ -177,11 +178,15 @@ class System:
 
 
 class Weights:
-    """ln W(E) = -beta_k E + alpha_k on bins of width eps above e_lo (Eq. 8)."""
+    """ln W(E) = -beta_k E + alpha_k on bins of width eps above e_lo (Eq. 8).  edge_tol > 0: a
+    walker whose starting energy lies at most edge_tol outside the window starts in the edge bin
+    on that side instead of being refused (the window-edge reading for energies left just outside
+    by reduced-precision accumulation)."""
 
     def __init__(self, e_lo, bin_width, n_bins, beta=None, alpha=None, g=None, beta_min=0.0,
-                 beta_max=0.0):
+                 beta_max=0.0, edge_tol=0.0):
         self.beta_min, self.beta_max = float(beta_min), float(beta_max)
+        self.edge_tol = float(edge_tol)
         self.e_lo = float(e_lo)
         self.bin_width = float(bin_width)
         self.n_bins = int(n_bins)
@@ -191,7 +196,7 @@ class Weights:
 
     def _c(self):
         return _Weights(self.e_lo, self.bin_width, self.n_bins, _p(self.beta, C.c_double),
-                        _p(self.alpha, C.c_double))
+                        _p(self.alpha, C.c_double), self.edge_tol)
 
     def berg_update(self, hist):
         hist = np.ascontiguousarray(hist, dtype=np.uint64)
@@ -201,7 +206,7 @@ class Weights:
 
     def copy(self):
         return Weights(self.e_lo, self.bin_width, self.n_bins, self.beta, self.alpha, self.g,
-                       self.beta_min, self.beta_max)
+                       self.beta_min, self.beta_max, self.edge_tol)
 
 
 def flatness(hist):

@@ -89,6 +89,8 @@ typedef struct {
     double e_lo, bin_width;
     int32_t n_bins;
     const double *beta, *alpha;  /* ln W(E) = -beta[k] E + alpha[k], k = bin of E (Eq. 8) */
+    double edge_tol;             /* a starting energy up to edge_tol outside the window is
+                                    counted in the edge bin (0: none); see start_bin */
 } orc_weights;
 
 typedef struct {
@@ -271,6 +273,20 @@ static int64_t bin_of(const orc_weights *w, double e)
     return (int64_t)floor(t);
 }
 
+/* Bin of a walker's starting energy: its bin inside the window; otherwise, when the energy lies at
+ * most edge_tol outside it, the edge bin on that side (ln W then extends that bin's line); -1
+ * beyond.  This is the window-edge reading for energies that reduced-precision accumulation can
+ * leave just outside the window; with edge_tol = 0 it is bin_of. */
+static int64_t start_bin(const orc_weights *w, double e)
+{
+    int64_t k = bin_of(w, e);
+    if (k >= 0 || !(w->edge_tol > 0.0)) return k;
+    const double top = w->e_lo + (double)w->n_bins * w->bin_width;
+    if (e >= w->e_lo - w->edge_tol && e < top + w->edge_tol)
+        return (e - w->e_lo) * (1.0 / w->bin_width) < 0.0 ? 0 : w->n_bins - 1;
+    return -1;
+}
+
 /* ln W(E) of Eq. (8), continuous and piecewise linear in E. */
 static double ln_weight(const orc_weights *w, double e, int64_t k)
 {
@@ -372,7 +388,7 @@ int orc_run(const orc_system *s, const orc_weights *w, const orc_moves *mv, uint
     walker_key(seed, walker, &k0, &k1);
     const int n = s->n_beads;
     double e = *energy;
-    int64_t k = bin_of(w, e);
+    int64_t k = start_bin(w, e);
     if (k < 0) return -1;
     double newpos[3], saved[3];
     int64_t logged = 0, since_check = 0;

@@ -430,6 +430,60 @@ def test_window_edge_tolerance(lib, pack):
         m.close()
 
 
+@pytest.mark.parametrize("side", ["top", "bottom"])
+@pytest.mark.parametrize("pack", [1, 2])
+def test_fp64_running_energy_just_outside_the_window_matches_oracle(lib, orc, side, pack):
+    """The window-edge rule against the reference's edge reading (edge_tol = 1e-3), move for
+    move in FP64: every walker's running energy is set 5e-4 outside the window, as FP32
+    accumulation can leave it at an edge until the next resync.  Both sides continue from the edge
+    bin with that energy (ln W extends the bin's line), count their moves there until a move
+    enters the window, and must agree in accept sequences, histograms and coordinates."""
+    import struct
+    wl = workloads.single_chain()
+    sp = wl.systems[0]
+    s = orc.System.from_workload(wl)
+    K = sp.n_bins
+    beta = np.full(K, 1 / 0.7)
+    # a random coil (from the straight start nearly every move raises the energy)
+    Wc = orc.Weights(sp.e_lo, wl.bin_width, K, beta, np.zeros(K))
+    wc = orc.Walker(s, workloads.initial_positions(wl)[0], 7, wl.seed)
+    wc.run(Wc, orc.move_params(wl), 200, np.zeros(K, np.uint64))
+    coil = wc.pos.copy()
+    top = sp.e_lo + K * wl.bin_width
+    e_start = top + 5e-4 if side == "top" else sp.e_lo - 5e-4
+    n_walk, n_sweeps = 4, 60
+    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=n_walk, precision=0,
+                               walkers_per_wave=pack)
+    m.set_weights(0, beta, np.zeros(K), np.zeros(K))
+    m.set_walkers(0, np.repeat(coil[None], n_walk, axis=0))
+    blob = bytearray(m.get_state())
+    n_pos = struct.unpack_from("6Q", blob, 0)[2]
+    for i in range(n_walk):
+        struct.pack_into("d", blob, 48 + 8 * n_pos + 8 * i, e_start)
+    m.set_state(bytes(blob))
+    n_log = n_sweeps * sp.n_beads
+    m.set_accept_log(n_log)
+    m.sweep(n_sweeps)
+    W = orc.Weights(sp.e_lo, wl.bin_width, K, beta, np.zeros(K), edge_tol=1e-3)
+    H = np.zeros(K, np.uint64)
+    log_g = m.accept_log(0)
+    pos_g, e_g, cnt = m.walkers_state(0)
+    edge = K - 1 if side == "top" else 0
+    for i in range(n_walk):
+        ow = orc.Walker(s, coil, i, wl.seed)
+        ow.energy = e_start
+        log = np.zeros(n_log, np.uint8)
+        h_before = int(H[edge])
+        ow.run(W, orc.move_params(wl), n_sweeps, H, accept_log=log)
+        assert int(H[edge]) > h_before, "no move counted in the edge bin"
+        assert np.array_equal(log_g[i], log), f"accept sequence of walker {i} differs"
+        assert np.allclose(pos_g[i], ow.pos, rtol=0, atol=1e-10)
+        assert e_g[i] == pytest.approx(ow.energy, abs=1e-9)
+        assert cnt["window_rejects"][i] == ow.counters.window_rejects
+    assert np.array_equal(m.histogram(0), H)
+    m.close()
+
+
 def test_discontinuous_weights_fall_back_to_one_walker_per_wave(lib, orc):
     """Two walkers per wave read ln W from its bin-edge values, which needs continuous weights.
     Random (discontinuous) beta, alpha switch the context to one walker per wave, whose sweep still
