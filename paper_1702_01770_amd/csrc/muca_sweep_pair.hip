@@ -25,9 +25,9 @@ size_t sweep_pair_lds_bytes(long long bins_total, int n_sys, int n_waves, int gr
     const size_t stage = (size_t)n_waves * pair_slab_stage(group);
     const size_t coord = (size_t)n_waves * pair_slab_coord(group, slots);
     return 2 * sizeof(double2) * kMaxTypes * kMaxTypes + sizeof(double) * kAngcEntries +
-           sizeof(Staged) * stage + sizeof(double) * kMaxTypes * kMaxTypes + sizeof(double) * coord +
+           sizeof(StagedMove) * stage + sizeof(double) * kMaxTypes * kMaxTypes + sizeof(double) * coord +
            sizeof(double) * (size_t)(bins_total + n_sys) + sizeof(unsigned int) * (size_t)bins_total +
-           sizeof(StagedBead) * stage + sizeof(int) * (size_t)n_sys * kMaxBeads;
+           sizeof(int) * (size_t)n_sys * kMaxBeads;
 }
 
 hipError_t launch_sweep_pair(const SweepArgs &a, bool fp64, int group, int slots, bool periodic,

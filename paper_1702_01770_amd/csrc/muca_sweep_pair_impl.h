@@ -175,7 +175,8 @@ struct Staged {
     double q0, q1, q2, lnu;
 };
 
-// Entries of the bending / torsion coefficient table (4 variants of 8).
+// Entries of the bending / torsion coefficient table (4 variants of 8): variant first + 2 last of
+// the moved bead b, entry j - b + 4 for bead j of b's chain, j = b-4 .. b+3 (the two ends zero).
 constexpr int kAngcEntries = 32;
 
 // Bead key j + 256 c of bead j in chain c: keys of beads in different chains differ by more than
@@ -183,11 +184,26 @@ constexpr int kAngcEntries = 32;
 __device__ __forceinline__ int bead_key(int j, int inf) { return j + 256 * bi_chain(inf); }
 
 // Per-move values of the moved bead b, staged with the draws: its key, its descriptor (with the
-// type byte replaced by the byte offset of the type's column in the coupling table) and its
-// bonded neighbours (b itself in place of a missing one at a chain end).
+// type byte replaced by the byte offset of the type's column in the coupling table, and the byte
+// offset of its variant in the bending / torsion coefficient table in bits 24-31, zero unless b
+// ends its chain) and its bonded neighbours (b itself in place of a missing one at a chain end).
 struct StagedBead {
     int key, inf, bm, bp;
 };
+
+// One staged move: the draws of move i and, 32 bytes further, the bead of move i; one address
+// reaches the draws of move i and the bead of move i + 1.
+struct alignas(16) StagedMove {
+    Staged q;
+    StagedBead b;
+};
+
+// The staged descriptor of a bead (StagedBead::inf) from its descriptor.
+template <typename A, typename A2>
+__device__ __forceinline__ int staged_inf(int inf) {
+    const int variant = (bi_first(inf) ? 1 : 0) + (bi_last(inf) ? 2 : 0);
+    return (inf & ~0xff) | (bi_type(inf) * (int)sizeof(A2)) | ((variant * 8 * (int)sizeof(A)) << 24);
+}
 
 struct PairLds {
     const double *lw;          // ln W at the K + 1 bin edges of this walker's system
@@ -196,9 +212,8 @@ struct PairLds {
     double *x, *y, *z;         // this walker's coordinates
     const double *ctab;        // C_LJ[t][u], t, u < kMaxTypes
     const void *kc;            // {kappa, kappa C_LJ}[intra / inter][t][u] in the accumulator type
-    const void *angc;          // bending / torsion coefficients of u_j . m, [first + 2 last][j - b + 3]
-    StagedBead *sb;            // staged moved beads of the next G moves (+1 spare)
-    Staged *sq;                // staged random values of the next G moves (+1 spare)
+    const void *angc;          // bending / torsion coefficients of u_j . m, [first + 2 last][j - b + 4]
+    StagedMove *st;            // staged draws and moved beads of the next G moves (+1 spare)
 };
 
 // This lane's beads j = gl + G s from the LDS mirror (slots past the last bead hold zeros).
@@ -323,9 +338,17 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
     }
     double lnw_cur = lnw_at(L.lw, k, (E - e_lo) * inv_eps);
 
-    unsigned int n_mv = 0, n_acc = 0, n_rig = 0, n_rig_acc = 0, n_wrej = 0, run = 0;
+    unsigned int n_mv = 0, n_acc = 0, n_rig = 0, n_rig_acc = 0, n_wrej = 0;
+    // histogram runs: n_all counts every move of the launch (the same in every group of the
+    // wave, so a scalar), mark is its value at the walker's last change of bin; the run in the
+    // current bin is n_all - mark
+    unsigned int n_all = 0, mark = 0;
     unsigned int n_piv = 0, n_piv_acc = 0, n_rot = 0, n_rot_acc = 0;
     double max_drift = a.drift[w];
+    // sweeps until the next FP64 recomputation (the sweep counter reaches a multiple of
+    // resync_sweeps), counted down instead of a 64-bit remainder every sweep
+    int to_resync = a.resync_sweeps > 0
+                        ? a.resync_sweeps - (int)(S % (unsigned long long)a.resync_sweeps) : 0;
     const long long total = n_sweeps * (long long)N;
     long long done = 0;
     int m = 0;
@@ -360,18 +383,16 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 q.q0 = cs; q.q1 = sn; q.q2 = 0.0;      // cosine, sine
             }
             q.lnu = log(u3);
-            L.sb[gl] = StagedBead{bead_key(blane, binf_l),
-                                  (binf_l & ~0xff) | (bi_type(binf_l) * (int)sizeof(A2)),
-                                  fs ? blane : blane - 1, ls ? blane : blane + 1};
-            L.sq[gl] = q;
+            L.st[gl].b = StagedBead{bead_key(blane, binf_l), staged_inf<A, A2>(binf_l),
+                                    fs ? blane : blane - 1, ls ? blane : blane + 1};
+            L.st[gl].q = q;
             if (gl == 0) {                          // spare entry for the last prefetch
                 const int i0 = L.binfo[0];
-                L.sb[G] = StagedBead{bead_key(0, i0), (i0 & ~0xff) | (bi_type(i0) * (int)sizeof(A2)),
-                                     0, 0};
+                L.st[G].b = StagedBead{bead_key(0, i0), staged_inf<A, A2>(i0), 0, 0};
             }
             __builtin_amdgcn_wave_barrier();
         }
-        StagedBead bi_nx = L.sb[0];
+        StagedBead bi_nx = L.st[0].b;
 
         for (int i = 0; i < nblk; ++i) {
             // everything read here depends only on the staged draw of this move, so all of it is
@@ -384,13 +405,15 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             const double xmx = L.x[bm], xmy = L.y[bm], xmz = L.z[bm];
             const double xpx = L.x[bp], xpy = L.y[bp], xpz = L.z[bp];
             const double xbx = L.x[b], xby = L.y[b], xbz = L.z[b];
-            const Staged q = L.sq[i];
-            bi_nx = L.sb[i + 1];
+            const StagedMove *sti = reinterpret_cast<const StagedMove *>(
+                reinterpret_cast<const char *>(L.st) + (unsigned)i * (unsigned)sizeof(StagedMove));
+            const Staged q = sti[0].q;
+            bi_nx = sti[1].b;
             const int tbo = infb & 0xff, cb = bi_chain(infb);   // b's column, in bytes
             // coupling of every slot's bead with b, and the coefficient of u_j . m for
-            // j = b-3 .. b+2 of the same chain (0 elsewhere: entry 6)
-            // (first ? 8 : 0) + (last ? 16 : 0) from descriptor bits 16 and 17
-            const A *act = reinterpret_cast<const A *>(L.angc) + ((infb >> 13) & 0x18);
+            // j = b-3 .. b+2 of the same chain (0 elsewhere); b's variant of the coefficient
+            // table from the staged descriptor's top byte
+            const char *act = reinterpret_cast<const char *>(L.angc) + ((unsigned)infb >> 24);
             A2 kk[SLOTS];
             A coef[SLOTS];
             double px[SLOTS], py[SLOTS], pz[SLOTS];
@@ -400,8 +423,10 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 const bool same = chn[s] == cb;
                 kk[s] = *reinterpret_cast<const A2 *>(
                     reinterpret_cast<const char *>(kct + (same ? 0 : kMaxTypes * kMaxTypes) + trow[s]) + tbo);
-                // entry j - b + 3 for j = b-3 .. b+2 of b's chain, 6 (zero) for every other bead
-                coef[s] = act[min((unsigned)(kp1[s] - bkey + 2), 6u)];
+                // entry j - b + 4: the key difference j + 1 - b clamped to [-3, 4] (one v_med3),
+                // so that every bead beyond b-4 .. b+3 or in another chain reads a zero end entry
+                const int e = min(max(kp1[s] - bkey, -3), 4);
+                coef[s] = *reinterpret_cast<const A *>(act + (e + 3) * (int)sizeof(A));
             }
             double nx, ny, nz;
             if ((unsigned)infb > 0xffffu) {         // first or last bead (descriptor bits 16, 17)
@@ -483,13 +508,13 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
             A bmx = (A)(nx - xmx), bmy = (A)(ny - xmy), bmz = (A)(nz - xmz);
             A bpx = (A)(xpx - nx), bpy = (A)(xpy - ny), bpz = (A)(xpz - nz);
             asm volatile("" : "+v"(bmx), "+v"(bmy), "+v"(bmz), "+v"(bpx), "+v"(bpy), "+v"(bpz),
-                         "+v"(ft), "+v"(l0), "+v"(l1));
-            const double lnw_new = l0 + (l1 - l0) * ft;
+                         "+v"(ft), "+v"(l0));
+            const double lnw_new = fma(ft, l1 - l0, l0);
             bool accept = inwin && (q.lnu < lnw_new - lnw_cur);
             // steric sphere: a bead may not leave it (the test is uniform over the launch)
             if (GEN && a.sphere_r2 > 0.0)
                 accept = accept && nx * nx + ny * ny + nz * nz <= a.sphere_r2;
-            n_wrej += inwin ? 0u : 1u;
+            if (__builtin_expect(!inwin, 0)) ++n_wrej;      // rare: a branch, not a select
             if (GEN && alog != nullptr) {
                 if (accept && gl == 0) {
                     // bit of this move: moves since the log was armed (the walker's move counter
@@ -514,13 +539,13 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 }
                 L.x[b] = nx; L.y[b] = ny; L.z[b] = nz;      // every lane of the half writes
                 if (kn != k) {
-                    if (gl == 0) atomicAdd(&L.hist[k], run);
-                    run = 0;
+                    if (gl == 0) atomicAdd(&L.hist[k], n_all - mark);
+                    mark = n_all;
                 }
                 E = En; k = kn; lnw_cur = lnw_new;
                 ++n_acc;
             }
-            ++run;
+            ++n_all;
 
             if (++m == N) {
                 m = 0;
@@ -578,13 +603,13 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                                 L.x[ib] = xo + tx; L.y[ib] = yo + ty; L.z[ib] = zo + tz;
                             }
                             if (rkn != k) {
-                                if (gl == 0) atomicAdd(&L.hist[k], run);
-                                run = 0;
+                                if (gl == 0) atomicAdd(&L.hist[k], n_all - mark);
+                                mark = n_all;
                             }
                             E = rEn; k = rkn; lnw_cur = rlnw;
                             ++n_rig_acc;
                         }
-                        ++run;
+                        ++n_all;
                     }
                 }
                 if constexpr (CHAIN) {
@@ -739,13 +764,13 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                             }
                         }
                         if (pkn != k) {
-                            if (gl == 0) atomicAdd(&L.hist[k], run);
-                            run = 0;
+                            if (gl == 0) atomicAdd(&L.hist[k], n_all - mark);
+                            mark = n_all;
                         }
                         E = pEn; k = pkn; lnw_cur = plnw;
                         ++n_piv_acc;
                     }
-                    ++run;
+                    ++n_all;
                 }
                 // ---- rigid rotations of a whole chain about its centre ----
                 for (int rr = 0; M > 1 && rr < a.rotate_per_sweep; ++rr) {
@@ -821,17 +846,18 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                             }
                         }
                         if (rkn != k) {
-                            if (gl == 0) atomicAdd(&L.hist[k], run);
-                            run = 0;
+                            if (gl == 0) atomicAdd(&L.hist[k], n_all - mark);
+                            mark = n_all;
                         }
                         E = rEn; k = rkn; lnw_cur = rlnw;
                         ++n_rot_acc;
                     }
-                    ++run;
+                    ++n_all;
                 }
                 }   // CHAIN
                 ++S;
-                if (a.resync_sweeps > 0 && (S % (unsigned long long)a.resync_sweeps) == 0) {
+                if (a.resync_sweeps > 0 && --to_resync == 0) {
+                    to_resync = a.resync_sweeps;
                     const double Ef = full_energy_pair<G, SLOTS, PERIODIC>(a, N, L, inf);
                     const double dr = fabs(Ef - E);
                     max_drift = fmax(max_drift, dr);
@@ -839,8 +865,8 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                     const int kf = window_bin(Ef, e_lo, a.bin_width, inv_eps, K);
                     if (kf >= 0) {
                         if (kf != k) {
-                            if (gl == 0) atomicAdd(&L.hist[k], run);
-                            run = 0;
+                            if (gl == 0) atomicAdd(&L.hist[k], n_all - mark);
+                            mark = n_all;
                         }
                         E = Ef; k = kf;
                         lnw_cur = lnw_at(L.lw, k, (E - e_lo) * inv_eps);
@@ -853,7 +879,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
         done += nblk;
         __builtin_amdgcn_wave_barrier();        // staged entries are rewritten by the next block
     }
-    if (gl == 0 && run) atomicAdd(&L.hist[k], run);
+    if (gl == 0 && n_all != mark) atomicAdd(&L.hist[k], n_all - mark);
 
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -904,8 +930,7 @@ struct PairShared {
     unsigned int *hist;
     const int *binfo;
     double *coord;           // wave slabs of kSlabCoord doubles
-    Staged *sq;              // wave slabs of kSlabStage entries
-    StagedBead *sb;
+    StagedMove *st;          // wave slabs of kSlabStage entries
     int slab_coord, slab_stage;
 };
 
@@ -930,8 +955,7 @@ __device__ void pair_wave(const SweepArgs &a, const WorkItem &wi, int wave, cons
     L.ctab = sh.ctab;
     L.kc = sh.kc;
     L.angc = sh.angc;
-    L.sb = sh.sb + (size_t)wave * sh.slab_stage + grp * kStage;
-    L.sq = sh.sq + (size_t)wave * sh.slab_stage + grp * kStage;
+    L.st = sh.st + (size_t)wave * sh.slab_stage + grp * kStage;
     // the chain-move instance keeps both tests in its loop (one instance instead of two)
     if constexpr (CHAIN) {
         run_pair<FP64, G, SLOTS, PERIODIC, CHAIN, true>(a, sd, w0 + grp, L, n_sweeps);
@@ -944,9 +968,8 @@ __device__ void pair_wave(const SweepArgs &a, const WorkItem &wi, int wave, cons
 }
 
 // LDS layout (per workgroup), 16-byte items first: the {kappa, kappa C_LJ} table (intra, inter)
-// in the accumulator type; the bending / torsion coefficient table; the staged draws and the
-// staged moved beads (one slab each per wave); the C_LJ table; the coordinate mirrors (one slab
-// per wave); ln W at the bin edges of every system of the workgroup (system i at
+// in the accumulator type; the bending / torsion coefficient table; the staged moves (draws and
+// moved bead, one slab per wave); the C_LJ table; the coordinate mirrors (one slab per wave); ln W at the bin edges of every system of the workgroup (system i at
 // lds_off[i] + i); the 32-bit histograms (system i at lds_off[i]); the bead descriptors of every
 // system.
 // G > 0: every wave holds 64 / G walkers in groups of G lanes with SLOTS bead slots per lane.
@@ -966,9 +989,8 @@ __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_swe
     const int bins_total = wi.lds_off[ns - 1] + a.sys[wi.sys[ns - 1]].n_bins;
     A2 *kc = reinterpret_cast<A2 *>(lds_p);
     A *angc = reinterpret_cast<A *>(lds_p + 2 * kMaxTypes * kMaxTypes);
-    Staged *sq = reinterpret_cast<Staged *>(lds_p + 2 * kMaxTypes * kMaxTypes + kAngcEntries / 2);
-    StagedBead *sb = reinterpret_cast<StagedBead *>(sq + (size_t)n_waves * kSlabStage);
-    double *ctab = reinterpret_cast<double *>(sb + (size_t)n_waves * kSlabStage);
+    StagedMove *st = reinterpret_cast<StagedMove *>(lds_p + 2 * kMaxTypes * kMaxTypes + kAngcEntries / 2);
+    double *ctab = reinterpret_cast<double *>(st + (size_t)n_waves * kSlabStage);
     double *pc = ctab + kMaxTypes * kMaxTypes;
     double *lw = pc + (size_t)n_waves * kSlabCoord;
     unsigned int *hist = reinterpret_cast<unsigned int *>(lw + bins_total + ns);
@@ -1003,15 +1025,16 @@ __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_swe
         // torsion terms that pair one of them with another bond u_j change by a multiple of
         // u_j . m: j = b-3 torsion(b-3); j = b-2 bend(b-2) and, unless b ends its chain,
         // torsion(b-2); j = b+1 bend(b) and, unless b starts its chain, torsion(b-1);
-        // j = b+2 torsion(b).  Entries 2, 3, 6, 7 are zero (6 serves every other lane).
+        // j = b+2 torsion(b).  Entry j - b + 4 of each variant: entries 0 and 7 (j = b-4 and
+        // b+3, where every bead farther away or in another chain reads too) and 3, 4 are zero.
         const int i = threadIdx.x & 7;
         const bool first = (threadIdx.x >> 3) & 1, last = (threadIdx.x >> 4) & 1;
         const A kb = (A)a.k_bend, kt = (A)a.k_tors;
         A c = (A)0;
-        if (i == 0) c = -kt;
-        if (i == 1) c = last ? -kb : -kb + kt;
-        if (i == 4) c = first ? kb : kb - kt;
-        if (i == 5) c = kt;
+        if (i == 1) c = -kt;
+        if (i == 2) c = last ? -kb : -kb + kt;
+        if (i == 5) c = first ? kb : kb - kt;
+        if (i == 6) c = kt;
         angc[threadIdx.x] = c;
     }
     const int wave = threadIdx.x >> 6;
@@ -1027,7 +1050,7 @@ __global__ void __launch_bounds__(512) k_sweep_pair(SweepArgs a, long long n_swe
     __syncthreads();
     PairShared sh;
     sh.kc = kc; sh.angc = angc; sh.ctab = ctab; sh.lw = lw; sh.hist = hist; sh.binfo = binfo;
-    sh.coord = pc; sh.sq = sq; sh.sb = sb;
+    sh.coord = pc; sh.st = st;
     sh.slab_coord = kSlabCoord; sh.slab_stage = kSlabStage;
     if constexpr (G > 0) {
         pair_wave<FP64, G, SLOTS, PERIODIC, CHAIN>(a, wi, wave, sh, n_sweeps);
