@@ -305,7 +305,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
     // lane state: bond to the next bead of the chain (accumulator type), descriptor, chain and
     // row offset into the coupling table; the coordinates themselves live in the LDS mirror only
     A ux[SLOTS], uy[SLOTS], uz[SLOTS];
-    int inf[SLOTS], chn[SLOTS], trow[SLOTS], kp1[SLOTS], kb1[SLOTS];
+    int inf[SLOTS], chn[SLOTS], trow[SLOTS], kp1[SLOTS], kb1[SLOTS], kb0[SLOTS];
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const int j = gl + G * s;
@@ -314,9 +314,11 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
         chn[s] = bi_chain(inf[s]);
         trow[s] = bi_type(inf[s]) * kMaxTypes;
         // bead key + 1 (far from every key in empty lanes); the same for the lane's bond to the
-        // next bead, far from every key where there is none
+        // next bead, far from every key where there is none, and that minus one (so that both
+        // "the bond ends at b" and "the bond starts at b" are one comparison with b's key)
         kp1[s] = alive ? bead_key(j, inf[s]) + 1 : 0x40000000;
         kb1[s] = alive && !bi_last(inf[s]) ? kp1[s] : 0x40000000;
+        kb0[s] = kb1[s] - 1;
         if (alive && !bi_last(inf[s])) {
             ux[s] = (A)(L.x[j + 1] - L.x[j]);
             uy[s] = (A)(L.y[j + 1] - L.y[j]);
@@ -532,16 +534,15 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
 #pragma unroll
                 for (int s = 0; s < SLOTS; ++s) {
                     // the lane's bond ends at b (bond b-1) or starts at b (bond b)
-                    const bool lo_b = kb1[s] == bkey, at_b = kb1[s] == bkey + 1;
+                    const bool lo_b = kb1[s] == bkey, at_b = kb0[s] == bkey;
                     ux[s] = lo_b ? bmx : (at_b ? bpx : ux[s]);
                     uy[s] = lo_b ? bmy : (at_b ? bpy : uy[s]);
                     uz[s] = lo_b ? bmz : (at_b ? bpz : uz[s]);
                 }
                 L.x[b] = nx; L.y[b] = ny; L.z[b] = nz;      // every lane of the half writes
-                if (kn != k) {
-                    if (gl == 0) atomicAdd(&L.hist[k], n_all - mark);
-                    mark = n_all;
-                }
+                const bool chg = kn != k;
+                if (chg && gl == 0) atomicAdd(&L.hist[k], n_all - mark);
+                mark = chg ? n_all : mark;                  // one select with a scalar operand
                 E = En; k = kn; lnw_cur = lnw_new;
                 ++n_acc;
             }
