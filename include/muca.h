@@ -57,7 +57,8 @@ enum { MUCA_PREC_FP64 = 0, MUCA_PREC_FP32_SPLIT = 1 };
  * Energy window of system s: [e_lo[s], e_lo[s] + n_bins[s] * bin_width), bins of width
  * bin_width; ln W(E) = -beta_k E + alpha_k (Eq. 8), starting from W = 1.
  * Moves: one sweep = N single-bead trial moves (end bead: bond along d + cap_rho g with g
- * uniform on the sphere; interior bead: crankshaft by an angle uniform in +-crank_max), then
+ * uniform on the sphere; interior bead: crankshaft by an angle uniform in +-crank_max, with
+ * |crank_max| <= 1e5, else MUCA_E_INVAL), then
  * rigid_per_sweep translations of a random chain by up to +-trans_max per axis when the system
  * has more than one chain, pivot_per_sweep pivots (the beads on one side of a random bead p of
  * its chain turn about x_p by an angle uniform in +-pivot_max about an axis uniform on the

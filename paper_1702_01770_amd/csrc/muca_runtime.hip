@@ -459,6 +459,8 @@ static int validate(const muca_config *c, std::string &why) {
     if (c->walkers_per_wave > 1 && (c->walkers_per_system % c->walkers_per_wave) != 0) { why = "walkers_per_system must be a multiple of walkers_per_wave"; return MUCA_E_INVAL; }
     if ((c->walkers_per_wave > 1 || c->walkers_per_wave == kPackMixed) && c->waves_per_block > 8) { why = "more than one walker per wave allows at most 8 waves per block"; return MUCA_E_INVAL; }
     if (!std::isfinite(c->beta_min) || !std::isfinite(c->beta_max)) { why = "beta bounds must be finite"; return MUCA_E_INVAL; }
+    // the sweep kernels' sincos of the move angle is accurate for arguments below 2^20
+    if (!std::isfinite(c->crank_max) || std::fabs(c->crank_max) > 1e5) { why = "crank_max must be finite with |crank_max| <= 1e5"; return MUCA_E_INVAL; }
     return MUCA_OK;
 }
 

@@ -6,14 +6,14 @@
 
 #include <cmath>
 
-// sin x and cos x for |x| < 2^20 (the move angles: |x| <= 2 pi).  Cody and Waite's reduction
-// x = k pi/2 + r, k = rint(2 x / pi), with pi/2 split in two doubles: x - k (pi/2)_hi is exact
-// under the fused multiply-add, and rl carries the rounding of r.  On |r| <= pi/4 the Taylor
-// series of sin to r^17 and of cos to r^18 (the next terms are below 1e-19); 1 - r^2/2 is formed
-// with its roundings carried.  The error stays below one unit in the last place, and
-// sin^2 + cos^2 - 1 has no bias (at most 0.8 / 0.9 ulp over 2e7 arguments in [-pi, 2 pi]), in a
-// fraction of the instructions of the library sincos, which also evaluates its large-argument
-// reduction.
+// sin x and cos x for |x| < 2^20 (the move angles: |x| <= 2 pi; beyond 2^20 the reduction loses
+// accuracy; crank_max is validated below 1e5).  Cody and Waite's reduction x = k pi/2 + r,
+// k = rint(2 x / pi), with pi/2 split in two doubles: x - k (pi/2)_hi is exact under the fused
+// multiply-add, and rl carries the rounding of r.  On |r| <= pi/4 the Taylor series of sin to
+// r^17 and of cos to r^18 (the next terms are below 1e-19); 1 - r^2/2 is formed with its
+// roundings carried.  The error stays below one unit in the last place, and sin^2 + cos^2 - 1 has
+// no bias (at most 0.8 / 0.9 ulp over 2e7 arguments in [-pi, 2 pi]), in a fraction of the
+// instructions of the library sincos, which also evaluates its large-argument reduction.
 __host__ __device__ inline void sincos_move(double x, double *sn, double *cs) {
     const double k = __builtin_rint(x * 0.6366197723675814);          // 2 / pi
     const double rh = std::fma(-k, 1.5707963267948966, x);            // exact

@@ -53,3 +53,18 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(L, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         L.load()
+
+
+def test_init_rejects_an_unbounded_crank_angle():
+    """The configuration is validated before any device call: a crankshaft range beyond what the
+    sweep kernels' move-angle sincos covers (|crank_max| <= 1e5) is refused with MUCA_E_INVAL."""
+    import numpy as np
+    import paper_1702_01770_amd as P
+    lib = os.path.join(ROOT, "paper_1702_01770_amd", "libmuca.so")
+    if not os.path.exists(lib):
+        pytest.skip("libmuca.so not built (run __graft_entry__.build())")
+    pos = np.stack([np.arange(6.0), np.zeros(6), np.zeros(6)], axis=1)
+    for bad in (1e6, float("inf"), float("nan")):
+        with pytest.raises(RuntimeError, match="crank_max"):
+            P.Muca([1], [6], [0, 1, 0, 1, 0, 1], pos, np.array([[1.0, -0.5], [-0.5, 0.5]]),
+                   [-10.0], [200], walkers_per_system=1, crank_max=bad)
