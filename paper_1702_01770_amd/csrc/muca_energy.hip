@@ -99,26 +99,36 @@ __global__ void __launch_bounds__(64 * kEWaves) k_energy_fwd(EnergyArgs a, Theta
     const float L = (float)a.box_len, invL = (float)a.inv_box;
     const int row = lane >> 4, seg = lane & 15, nm = (N + 15) >> 4;
     float qx[kSlots], qy[kSlots], qz[kSlots];
-    int qi[kSlots];
+    // bead i's chain (descriptor byte 1, in place) and the byte offsets of its type's row in the
+    // coupling table for a partner of the same or another chain, so that a pair's entry is one
+    // compare, one select and one add away (the empty asm keeps them in registers instead of
+    // rederiving them from the descriptor for every pair)
+    int qc[kSlots], qa[kSlots], qb[kSlots];
 #pragma unroll
     for (int m = 0; m < kSlots; ++m) {
         const int i = seg + 16 * m;
         const float4 q = xs[i < N ? i : N - 1];
-        qx[m] = q.x; qy[m] = q.y; qz[m] = q.z; qi[m] = info_of(q);
+        qx[m] = q.x; qy[m] = q.y; qz[m] = q.z;
+        qc[m] = info_of(q) & 0xff00;
+        qa[m] = bi_type(info_of(q)) * kMaxTypes * (int)sizeof(float2);
+        qb[m] = qa[m] + kMaxTypes * kMaxTypes * (int)sizeof(float2);
+        asm volatile("" : "+v"(qc[m]), "+v"(qa[m]), "+v"(qb[m]));
     }
     double e_acc = 0.0;
     for (int jb = 0; jb < N; jb += 4) {
         const int j = jb + row;
         const bool jl = j < N;
         const float4 pj = xs[jl ? j : N - 1];
-        const int infj = info_of(pj), cj = bi_chain(infj), tj = bi_type(infj);
+        const int infj = info_of(pj), cjb = infj & 0xff00;
+        int tjb = bi_type(infj) * (int)sizeof(float2);
+        asm volatile("" : "+v"(tjb));
         const int m0 = jb >> 4;
         float e = 0.0f;
 #pragma unroll
         for (int m = 0; m < kSlots; ++m) {
             if (m < m0 || m >= nm) continue;
             const int i = seg + 16 * m;
-            const bool same = bi_chain(qi[m]) == cj;
+            const bool same = qc[m] == cjb;
             const bool use = jl && i > j && i < N && !(same && i == j + 1);
             const float dx = sep<PERIODIC>(pj.x - qx[m], L, invL);
             const float dy = sep<PERIODIC>(pj.y - qy[m], L, invL);
@@ -126,7 +136,8 @@ __global__ void __launch_bounds__(64 * kEWaves) k_energy_fwd(EnergyArgs a, Theta
             const float r2 = use ? dx * dx + dy * dy + dz * dz : 1.0f;
             const float sr = __builtin_amdgcn_rcpf(r2);
             const float s3 = use ? sr * sr * sr : 0.0f;
-            const float2 k = coef[(same ? 0 : kMaxTypes * kMaxTypes) + bi_type(qi[m]) * kMaxTypes + tj];
+            const float2 k = *reinterpret_cast<const float2 *>(
+                reinterpret_cast<const char *>(coef) + (same ? qa[m] : qb[m]) + tjb);
             e += s3 * (k.x * s3 + k.y);
         }
         e_acc += (double)e;
@@ -174,12 +185,16 @@ __global__ void __launch_bounds__(64 * kEWaves) k_energy_bwd(EnergyArgs a, Theta
     const float L = (float)a.box_len, invL = (float)a.inv_box;
     const int row = lane >> 4, seg = lane & 15, nm = (N + 15) >> 4;
     float qx[kSlots], qy[kSlots], qz[kSlots], fx[kSlots], fy[kSlots], fz[kSlots];
-    int qi[kSlots];
+    int qc[kSlots], qa[kSlots], qb[kSlots];      // as in k_energy_fwd (entries of float4)
 #pragma unroll
     for (int m = 0; m < kSlots; ++m) {
         const int i = seg + 16 * m;
         const float4 q = xs[i < N ? i : N - 1];
-        qx[m] = q.x; qy[m] = q.y; qz[m] = q.z; qi[m] = info_of(q);
+        qx[m] = q.x; qy[m] = q.y; qz[m] = q.z;
+        qc[m] = info_of(q) & 0xff00;
+        qa[m] = bi_type(info_of(q)) * kMaxTypes * (int)sizeof(float4);
+        qb[m] = qa[m] + kMaxTypes * kMaxTypes * (int)sizeof(float4);
+        asm volatile("" : "+v"(qc[m]), "+v"(qa[m]), "+v"(qb[m]));
         fx[m] = fy[m] = fz[m] = 0.0f;
     }
     double t_ab = 0.0, t_bb = 0.0, t_bend = 0.0, t_tors = 0.0;
@@ -187,14 +202,16 @@ __global__ void __launch_bounds__(64 * kEWaves) k_energy_bwd(EnergyArgs a, Theta
         const int j = jb + row;
         const bool jl = j < N;
         const float4 pj = xs[jl ? j : N - 1];
-        const int infj = info_of(pj), cj = bi_chain(infj), tj = bi_type(infj);
+        const int infj = info_of(pj), cjb = infj & 0xff00;
+        int tjb = bi_type(infj) * (int)sizeof(float4);
+        asm volatile("" : "+v"(tjb));
         const int m0 = jb >> 4;
         float gx = 0.0f, gy = 0.0f, gz = 0.0f, sab = 0.0f, sbb = 0.0f;
 #pragma unroll
         for (int m = 0; m < kSlots; ++m) {
             if (m < m0 || m >= nm) continue;
             const int i = seg + 16 * m;
-            const bool same = bi_chain(qi[m]) == cj;
+            const bool same = qc[m] == cjb;
             const bool use = jl && i > j && i < N && !(same && i == j + 1);
             const float dx = sep<PERIODIC>(pj.x - qx[m], L, invL);
             const float dy = sep<PERIODIC>(pj.y - qy[m], L, invL);
@@ -202,7 +219,8 @@ __global__ void __launch_bounds__(64 * kEWaves) k_energy_bwd(EnergyArgs a, Theta
             const float r2 = use ? dx * dx + dy * dy + dz * dz : 1.0f;
             const float sr = __builtin_amdgcn_rcpf(r2);
             const float s3 = use ? sr * sr * sr : 0.0f;
-            const float4 k = coef[(same ? 0 : kMaxTypes * kMaxTypes) + bi_type(qi[m]) * kMaxTypes + tj];
+            const float4 k = *reinterpret_cast<const float4 *>(
+                reinterpret_cast<const char *>(coef) + (same ? qa[m] : qb[m]) + tjb);
             // d/dx_j of kappa (r^-12 - C r^-6) = (-12 kappa s^3 + 6 kappa C) s^3 s d, s = 1/r^2;
             // bead i gets the opposite force
             const float f = (k.x * s3 + k.y) * s3 * sr;
