@@ -128,14 +128,16 @@ __device__ double energy_forces(const SweepArgs &a, HmcLds &L, const int *bi, co
         e += use ? ep : 0.0;
         const double fx = f * dx, fy = f * dy, fz = f * dz;
         gx += fx; gy += fy; gz += fz;
-        // lanes of one offset hit distinct partners: no two adds to one address at once
-        atomicAdd(&L.rx[i], -fx);
-        atomicAdd(&L.ry[i], -fy);
-        atomicAdd(&L.rz[i], -fz);
+        // lanes of one offset hit distinct partners: no two adds to one address at once; the
+        // partner's reaction -f is summed with the opposite sign and subtracted below (the same
+        // bits: negation is exact), so no lane negates its force before the add
+        atomicAdd(&L.rx[i], fx);
+        atomicAdd(&L.ry[i], fy);
+        atomicAdd(&L.rz[i], fz);
         i = i2; infi = infi2; xi = xi2; yi = yi2; zi = zi2;
     }
     __builtin_amdgcn_wave_barrier();
-    gx += L.rx[lane]; gy += L.ry[lane]; gz += L.rz[lane];
+    gx -= L.rx[lane]; gy -= L.ry[lane]; gz -= L.rz[lane];
     // bending (beads j, j+1, j+2) and torsion-like (j .. j+3) terms of this lane
     double dp[3] = {0, 0, 0}, dq[3] = {0, 0, 0}, ep[3] = {0, 0, 0}, eq[3] = {0, 0, 0};
     if (act && lane + 2 <= ce) {
