@@ -96,7 +96,11 @@ __device__ double energy_forces(const SweepArgs &a, HmcLds &L, const int *bi, co
     const double xj = L.x[act ? lane : 0], yj = L.y[act ? lane : 0], zj = L.z[act ? lane : 0];
     L.rx[lane] = 0.0; L.ry[lane] = 0.0; L.rz[lane] = 0.0;
     __builtin_amdgcn_wave_barrier();
-    const int infj = bi[lane], tj = bi_type(infj), cj = bi_chain(infj);
+    // bi holds the descriptors with the type byte replaced by the type's byte offset in a row of
+    // ct: this lane's row for a partner of the same chain (rj) or another (rj + the intra/inter
+    // stride), the partner's column from its type byte
+    const int infj = bi[lane], cj = bi_chain(infj);
+    const int rj = (infj & 0xff) * kMaxTypes;
     const int dmax = N / 2;
     // partner of offset d: i = lane + d mod N (always inside the 64-entry arrays); its bead info
     // and coordinates are requested one offset ahead, before the arithmetic of the current one
@@ -122,7 +126,9 @@ __device__ double energy_forces(const SweepArgs &a, HmcLds &L, const int *bi, co
         }
         const double r2 = use ? dx * dx + dy * dy + dz * dz : 1.0;
         const double s = recip(r2), s3 = s * s * s;
-        const double2 kc = ct[(same ? 0 : kMaxTypes * kMaxTypes) + tj * kMaxTypes + bi_type(infi)];
+        const double2 kc = *reinterpret_cast<const double2 *>(
+            reinterpret_cast<const char *>(ct) +
+            (same ? rj : rj + kMaxTypes * kMaxTypes * (int)sizeof(double2)) + (infi & 0xff));
         const double ep = s3 * (kc.x * s3 - kc.y);
         const double f = use ? (-12.0 * kc.x * s3 + 6.0 * kc.y) * s3 * s : 0.0;
         e += use ? ep : 0.0;
@@ -207,7 +213,7 @@ __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs 
     const int N = sd.n_beads, K = sd.n_bins;
     const bool act = lane < N;
     const int inf = act ? a.binfo[sys * kMaxBeads + lane] : bead_info(0, 255, true, true);
-    bi[lane] = inf;
+    bi[lane] = (inf & ~0xff) | (bi_type(inf) * (int)sizeof(double2));   // see energy_forces
     const bool first = bi_first(inf);
     const int cs = act ? sd.chain_start[bi_chain(inf)] : lane;
     const int ce = act ? sd.chain_start[bi_chain(inf) + 1] - 1 : lane;
