@@ -16,6 +16,7 @@
 // partner's LDS accumulator, in the same order on every call; angle terms once per lane,
 // gathered through LDS.
 #include "muca_internal.h"
+#include "muca_logu.h"
 
 namespace muca {
 
@@ -179,6 +180,14 @@ __device__ double energy_forces(const SweepArgs &a, HmcLds &L, const int *bi, co
     return wave_sum_d(e);
 }
 
+// A double that is the same in every lane, moved to scalar registers (both halves of lane 0).
+__device__ __forceinline__ double wave_uniform_d(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned int lo = __builtin_amdgcn_readfirstlane((unsigned int)b);
+    const unsigned int hi = __builtin_amdgcn_readfirstlane((unsigned int)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // Bin of e, edge bins extended (a non-finite energy maps to bin 0; such an end is rejected).
 __device__ __forceinline__ int bin_of(double e, double e_lo, double inv_eps, int K) {
     const double t = floor((e - e_lo) * inv_eps);
@@ -186,9 +195,9 @@ __device__ __forceinline__ int bin_of(double e, double e_lo, double inv_eps, int
     return t >= (double)K ? K - 1 : (int)t;
 }
 
-// At least four waves per SIMD (128 VGPRs; the compiler spills a few FP64 values outside the
-// pair loop): the 4096 walkers of the batched workload are then resident at once, which beats
-// two rounds at 195 registers (2.27 vs 2.61 ms for its 10 x 10-step trajectories).
+// At least four waves per SIMD (128 VGPRs, no spills): the 4096 walkers of the batched workload
+// are then resident at once, which beats two rounds at 195 registers (2.27 vs 2.61 ms for its
+// 10 x 10-step trajectories).
 template <bool PERIODIC>
 __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs h) {
     __shared__ HmcLds lds[kHmcWaves];
@@ -263,8 +272,10 @@ __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs 
         double Ec = energy_forces<PERIODIC>(a, L, bi, ct, N, lane, ce, gx, gy, gz);
         const double E0 = Ec;
         const int kb0 = bin_of(E0, e_lo, inv_eps, K);
-        const double H0 = -(-beta[kb0] * E0 + alpha[kb0]) +
-                          0.5 * wave_sum_d(mx * mx + my * my + mz * mz);
+        // H0 is uniform over the wave: held in scalar registers, so that neither it nor the
+        // coefficients it is formed from occupy vector registers across the leapfrog steps
+        const double H0 = wave_uniform_d(-(-beta[kb0] * E0 + alpha[kb0]) +
+                                         0.5 * wave_sum_d(mx * mx + my * my + mz * mz));
         auto gen_forces = [&](double Ecur, double &Gx, double &Gy, double &Gz) {
             const double b = beta[bin_of(Ecur, e_lo, inv_eps, K)];
             Gx = seg_suffix(-b * gx, lane, cs, ce);
@@ -319,7 +330,7 @@ __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs 
         const int k1b = bin_of(Ec, e_lo, inv_eps, K);
         const double H1 = -(-beta[k1b] * Ec + alpha[k1b]) + K1;
         const U4 ra = philox4x32_10(0u, (unsigned)T, (unsigned)(T >> 32), 8u, k0, k1);
-        const bool accept = inwin && inside && (log(u01(ra.x)) < H0 - H1);
+        const bool accept = inwin && inside && (log_unit(u01(ra.x)) < H0 - H1);
         n_wrej += inwin ? 0 : 1;
         if (accept) {
             if (act) { Pt[lane_t] = nx; Pt[a.npad + lane_t] = ny; Pt[2 * a.npad + lane_t] = nz; }
