@@ -73,8 +73,10 @@ enum { MUCA_PREC_FP64 = 0, MUCA_PREC_FP32_SPLIT = 1 };
  * groups of a wavefront (walkers_per_system a multiple of it, at most 8 waves per block; 4 also
  * needs at most 64 beads per system); MUCA_WALKERS_MIXED (-1) picks per system by chain length
  * (the longest chains one walker per wave, the shortest four, the rest two; walkers_per_system
- * a multiple of 4, at most 64 beads, 8 waves per block; init fails when no chain is long enough
- * to gain from it; muca_autotune also tries moving fewer of the longest chains to whole waves);
+ * a multiple of 4, at most 64 beads, waves_per_block waves per block (8 by default; every
+ * workgroup must be resident at once, at most one per compute unit, else MUCA_E_INVAL); init
+ * fails when no chain is long enough to gain from it; muca_autotune also tries moving fewer of
+ * the longest chains to whole waves, and blocks of 4 waves);
  * 0 lets the library choose (2 when possible).  Several
  * walkers per wave read ln W from its values at the bin edges, which needs continuous weights
  * (the two lines of Eq. 8 meeting at every inner bin edge agree there, as the weight recursion
@@ -234,8 +236,9 @@ int muca_set_state(muca_ctx *ctx, const void *buf, size_t bytes);
 
 /* Time the candidate sweep launches (one, two or four walkers per wave; 16, 8, 4, 2 or 1
  * waves per workgroup; with several systems, with and without pairing long and short chains in
- * one workgroup; last mixed plans with at most 1, 2, 3, 4, 6, 8 or all systems on whole waves,
- * which replace the best uniform plan only when more than 1 % faster) on probe_sweeps sweeps, keep the fastest and restore the sampling state, so
+ * one workgroup; last mixed plans with at most 1, 2, 3, 4, 6, 8 or all systems on whole waves
+ * in blocks of 8 waves, and with all of them in blocks of 4, which replace the best uniform plan
+ * only when more than 1 % faster) on probe_sweeps sweeps, keep the fastest and restore the sampling state, so
  * results do not depend on tuning (every walker's trajectory is independent of the schedule).
  * Candidates whose LDS does not fit are skipped.  *chosen (host, may be NULL) receives the waves
  * per workgroup, negated for an unpaired schedule; muca_get_launch_info gives the full plan. */

@@ -162,9 +162,11 @@ static int build_schedule(muca_ctx *ctx, int wpb, bool pair, int pack);
 // needs W / 2 more waves, made up by moving the shortest chains (N <= 32) to four walkers per
 // wave, so that all waves stay resident (8 per CU); chains of at most 16 beads always run four
 // per wave.  At most max64 systems move to whole waves (two waves on one SIMD share its issue
-// slots, so moving fewer can be faster; the autotuner tries several).  Fails when no system
-// would move.
-static int plan_mixed(muca_ctx *ctx, int max64) {
+// slots, so moving fewer can be faster; the autotuner tries several).  Workgroups of wpb waves,
+// all resident at once (at most one per CU): eight by default; four lets a workload of few
+// walkers spread its whole waves over every CU at one wave per SIMD instead of two waves per SIMD
+// on half of them.  Fails when no system would move.
+static int plan_mixed(muca_ctx *ctx, int max64, int wpb = 8) {
     const int n = ctx->n_sys, W = ctx->W;
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
@@ -201,7 +203,7 @@ static int plan_mixed(muca_ctx *ctx, int max64) {
         }
         if (moved == 0) break;
         ctx->kind = kind;
-        const int rc = build_schedule(ctx, 8, true, kPackMixed);
+        const int rc = build_schedule(ctx, wpb, true, kPackMixed);
         if (rc == MUCA_OK && ctx->n_items <= std::max(1, ctx->n_cu)) return MUCA_OK;
         if (rc != MUCA_OK && rc != MUCA_E_INVAL) return rc;
         ctx->err.clear();
@@ -708,7 +710,7 @@ int muca_init(const muca_config *cfg, muca_ctx **out) {
             ctx->err = "the mixed plan needs at most 64 beads per system";
             return bail(MUCA_E_INVAL);
         }
-        rc = plan_mixed(ctx, ctx->n_sys);
+        rc = plan_mixed(ctx, ctx->n_sys, cfg->waves_per_block > 0 ? cfg->waves_per_block : 8);
         if (rc != MUCA_OK) return bail(rc);
         *out = ctx;
         return MUCA_OK;
@@ -1165,6 +1167,7 @@ int muca_autotune(muca_ctx *ctx, int64_t probe_sweeps, int32_t *chosen) {
         for (int m64 : {1, 2, 3, 4, 6, 8})
             if (m64 < ctx->n_sys) cands.push_back(Cand{kPackMixed, 8, true, m64});
         cands.push_back(Cand{kPackMixed, 8, true, ctx->n_sys});
+        cands.push_back(Cand{kPackMixed, 4, true, ctx->n_sys});
     }
     Cand best{ctx->pack, ctx->wpb, ctx->paired, ctx->n_sys};
     float best_ms = 1e30f;
@@ -1172,7 +1175,7 @@ int muca_autotune(muca_ctx *ctx, int64_t probe_sweeps, int32_t *chosen) {
     CK(hipEventCreate(&e0));
     CK(hipEventCreate(&e1));
     for (const Cand &cd : cands) {
-        rc = cd.pack == kPackMixed ? plan_mixed(ctx, cd.max64)
+        rc = cd.pack == kPackMixed ? plan_mixed(ctx, cd.max64, cd.wpb)
                                    : build_schedule(ctx, cd.wpb, cd.pair, cd.pack);
         if (rc == MUCA_E_INVAL) { rc = MUCA_OK; continue; }   // does not fit in LDS
         if (rc != MUCA_OK) break;
@@ -1198,7 +1201,7 @@ int muca_autotune(muca_ctx *ctx, int64_t probe_sweeps, int32_t *chosen) {
     if (rc != MUCA_OK) return rc;
     rc = sync_and_check(ctx);
     if (rc != MUCA_OK) return rc;
-    rc = best.pack == kPackMixed ? plan_mixed(ctx, best.max64)
+    rc = best.pack == kPackMixed ? plan_mixed(ctx, best.max64, best.wpb)
                                  : build_schedule(ctx, best.wpb, best.pair, best.pack);
     if (rc != MUCA_OK) return rc;
     ctx->err.clear();

@@ -182,6 +182,20 @@ def test_fp64_mixed_plan(lib, orc, make, lanes):
     _compare(lib, orc, wl, walkers=8, n_sweeps=300, pack=-1)
 
 
+def test_fp64_mixed_plan_in_blocks_of_four_waves(lib, orc):
+    """The mixed plan in workgroups of four waves (one walker per wave for the 36-bead aggregate,
+    so that 1024 such walkers occupy every compute unit at one wave per SIMD): the same
+    trajectories as the reference, and the block size as asked."""
+    wl = workloads.aggregation()
+    m = lib.Muca.from_workload(wl, workloads.initial_positions(wl), walkers=8, precision=0,
+                               walkers_per_wave=-1, waves_per_block=4)
+    info = m.launch_info()
+    assert info["waves_per_block"] == 4 and info["lanes_used"] == 0b100, info
+    assert info["workgroups"] == 2, info
+    m.close()
+    _compare(lib, orc, wl, walkers=8, n_sweeps=300, pack=-1, waves_per_block=4)
+
+
 def test_fp64_mixed_plan_chain_moves(lib, orc):
     """The human cross-seeding mixture (38 beads, one walker per wave) in its sphere with
     rigid translations, pivots and chain rotations."""
