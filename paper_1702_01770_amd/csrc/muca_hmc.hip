@@ -180,7 +180,8 @@ __device__ double energy_forces(const SweepArgs &a, HmcLds &L, const int *bi, co
     return wave_sum_d(e);
 }
 
-// A double that is the same in every lane, moved to scalar registers (both halves of lane 0).
+// A double that is the same in every active lane, moved to scalar registers (both halves read
+// from the first active lane).
 __device__ __forceinline__ double wave_uniform_d(double v) {
     const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
     const unsigned int lo = __builtin_amdgcn_readfirstlane((unsigned int)b);
