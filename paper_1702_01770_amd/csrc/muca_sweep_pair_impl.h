@@ -149,6 +149,15 @@ __device__ __forceinline__ double rsqrt_pos(double x) {
     return fma(r * e, fma(e, 0.375, 0.5), r);
 }
 
+// 1 / x for finite x > 0: the hardware estimate refined by two Newton steps y <- y + y (1 - x y),
+// within the rounding level of FP64 (not always the correctly rounded quotient); no special-value
+// handling (x = 0 gives NaN, in lanes whose term is discarded).
+__device__ __forceinline__ double recip_pos(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+
 // v -> R v for the rotation by the angle with cosine co and sine sn about the unit axis k
 // (Rodrigues' formula).
 __device__ __forceinline__ void rot3(double kx, double ky, double kz, double co, double sn,
@@ -487,7 +496,7 @@ __device__ void run_pair(const SweepArgs &a, const SysDev &sd, int w, const Pair
                 const double r2n = dxn * dxn + dyn * dyn + dzn * dzn;
                 A so, sn2;
                 if constexpr (FP64) {
-                    so = 1.0 / r2o; sn2 = 1.0 / r2n;
+                    so = recip_pos(r2o); sn2 = recip_pos(r2n);
                 } else {
                     so = __builtin_amdgcn_rcpf((float)r2o);
                     sn2 = __builtin_amdgcn_rcpf((float)r2n);
