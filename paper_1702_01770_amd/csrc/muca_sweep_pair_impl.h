@@ -37,13 +37,22 @@ __device__ __forceinline__ double min_img(double d, double L, double invL) {
     return d - L * rint(d * invL);
 }
 
+// 1 / x for finite x > 0: the hardware estimate refined by two Newton steps y <- y + y (1 - x y),
+// within the rounding level of FP64 (not always the correctly rounded quotient); no special-value
+// handling (x = 0 gives NaN, in lanes whose term is discarded).
+__device__ __forceinline__ double recip_pos(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+
 template <bool FP64>
 __device__ __forceinline__ AccP<FP64> pair_d(double dxo, double dyo, double dzo, double dxn,
                                              double dyn, double dzn, double k, double kc) {
     if constexpr (FP64) {
         const double r2o = dxo * dxo + dyo * dyo + dzo * dzo;
         const double r2n = dxn * dxn + dyn * dyn + dzn * dzn;
-        const double so = 1.0 / r2o, sn = 1.0 / r2n;
+        const double so = recip_pos(r2o), sn = recip_pos(r2n);
         const double s3o = so * so * so, s3n = sn * sn * sn;
         return s3n * (k * s3n - kc) - s3o * (k * s3o - kc);
     } else {
@@ -147,15 +156,6 @@ __device__ __forceinline__ double rsqrt_pos(double x) {
     const double r = __builtin_amdgcn_rsq(x);
     const double e = fma(r * -x, r, 1.0);
     return fma(r * e, fma(e, 0.375, 0.5), r);
-}
-
-// 1 / x for finite x > 0: the hardware estimate refined by two Newton steps y <- y + y (1 - x y),
-// within the rounding level of FP64 (not always the correctly rounded quotient); no special-value
-// handling (x = 0 gives NaN, in lanes whose term is discarded).
-__device__ __forceinline__ double recip_pos(double x) {
-    double y = __builtin_amdgcn_rcp(x);
-    y = fma(y, fma(-x, y, 1.0), y);
-    return fma(y, fma(-x, y, 1.0), y);
 }
 
 // v -> R v for the rotation by the angle with cosine co and sine sn about the unit axis k
