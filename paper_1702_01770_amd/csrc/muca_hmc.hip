@@ -71,6 +71,15 @@ __device__ __forceinline__ double recip(double x) {
     return fma(y, fma(-x, y, 1.0), y);
 }
 
+// 1 / sqrt(x) for a positive normal x: the hardware estimate r refined by the second-order step
+// r (1 + e/2 + 3 e^2 / 8), e = 1 - x r^2 (the first terms of (1 - e)^(-1/2)), which leaves the
+// error at the rounding level of FP64.
+__device__ __forceinline__ double rsqrt_refined(double x) {
+    const double r = __builtin_amdgcn_rsq(x);
+    const double e = fma(r * -x, r, 1.0);
+    return fma(r * e, fma(e, 0.375, 0.5), r);
+}
+
 // Derivative of kappa (1 - p.q / (|p||q|)) with respect to the bonds p and q; returns 1 - cos.
 __device__ __forceinline__ double angle_grad(const double p[3], const double q[3], double kappa,
                                              double dp[3], double dq[3]) {
@@ -299,14 +308,18 @@ __global__ void __launch_bounds__(64 * kHmcWaves, 4) k_hmc(SweepArgs a, HmcArgs 
                 if (first) {
                     vx += hs * mx; vy += hs * my; vz += hs * mz;
                 } else {
-                    const double sp = sqrt(mx * mx + my * my + mz * mz);
+                    // |w| and 1 / |w| from one refined reciprocal square root (w = 0: |w| = 0 and
+                    // sin(|w| h) / |w| taken as 0, the limit times |w|, which multiplies it)
+                    const double q = mx * mx + my * my + mz * mz;
+                    const double rq = q > 0.0 ? rsqrt_refined(q) : 0.0;
+                    const double sp = q * rq;
                     double s, c;
                     sincos(sp * hs, &s, &c);
-                    const double is = s / (sp > 0.0 ? sp : 1.0);     // sin(|w| h) / |w|
+                    const double is = s * rq;                        // sin(|w| h) / |w|
                     double ux = vx * c + mx * is, uy = vy * c + my * is, uz = vz * c + mz * is;
                     double wx = mx * c - vx * (sp * s), wy = my * c - vy * (sp * s),
                            wz = mz * c - vz * (sp * s);
-                    const double inu = 1.0 / sqrt(ux * ux + uy * uy + uz * uz);
+                    const double inu = rsqrt_refined(ux * ux + uy * uy + uz * uz);
                     ux *= inu; uy *= inu; uz *= inu;
                     const double d = wx * ux + wy * uy + wz * uz;
                     wx -= d * ux; wy -= d * uy; wz -= d * uz;
