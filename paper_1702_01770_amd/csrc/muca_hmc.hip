@@ -83,14 +83,17 @@ __device__ __forceinline__ double rsqrt_refined(double x) {
 // Derivative of kappa (1 - p.q / (|p||q|)) with respect to the bonds p and q; returns 1 - cos.
 __device__ __forceinline__ double angle_grad(const double p[3], const double q[3], double kappa,
                                              double dp[3], double dq[3]) {
-    const double np = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
-    const double nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+    // 1/|p| and 1/|q| from refined reciprocal square roots, so that the unit vectors and the
+    // gradients are products
+    const double ip = rsqrt_refined(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    const double iq = rsqrt_refined(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
     double u[3], v[3];
-    for (int c = 0; c < 3; ++c) { u[c] = p[c] / np; v[c] = q[c] / nq; }
+    for (int c = 0; c < 3; ++c) { u[c] = p[c] * ip; v[c] = q[c] * iq; }
     const double cs = u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+    const double kp = -kappa * ip, kq = -kappa * iq;
     for (int c = 0; c < 3; ++c) {
-        dp[c] = -kappa * (v[c] - cs * u[c]) / np;
-        dq[c] = -kappa * (u[c] - cs * v[c]) / nq;
+        dp[c] = kp * (v[c] - cs * u[c]);
+        dq[c] = kq * (u[c] - cs * v[c]);
     }
     return 1.0 - cs;
 }
