@@ -28,8 +28,9 @@ __device__ __forceinline__ int info_of(float4 v) { return __builtin_bit_cast(int
 // Derivative of kappa (1 - p.q / (|p||q|)) with respect to the bonds p and q.
 __device__ __forceinline__ float bond_pair_grad(float3 p, float3 q, float kappa, float3 *dp,
                                                 float3 *dq) {
-    const float ip = 1.0f / sqrtf(p.x * p.x + p.y * p.y + p.z * p.z);
-    const float iq = 1.0f / sqrtf(q.x * q.x + q.y * q.y + q.z * q.z);
+    // the hardware reciprocal square root (about one unit in the last place of FP32)
+    const float ip = __builtin_amdgcn_rsqf(p.x * p.x + p.y * p.y + p.z * p.z);
+    const float iq = __builtin_amdgcn_rsqf(q.x * q.x + q.y * q.y + q.z * q.z);
     const float ux = p.x * ip, uy = p.y * ip, uz = p.z * ip;
     const float vx = q.x * iq, vy = q.y * iq, vz = q.z * iq;
     const float c = ux * vx + uy * vy + uz * vz;
@@ -41,7 +42,8 @@ __device__ __forceinline__ float bond_pair_grad(float3 p, float3 q, float kappa,
 
 __device__ __forceinline__ float cos_between(float3 p, float3 q) {
     const float pq = p.x * q.x + p.y * q.y + p.z * q.z;
-    return pq / sqrtf((p.x * p.x + p.y * p.y + p.z * p.z) * (q.x * q.x + q.y * q.y + q.z * q.z));
+    return pq * __builtin_amdgcn_rsqf((p.x * p.x + p.y * p.y + p.z * p.z) *
+                                      (q.x * q.x + q.y * q.y + q.z * q.z));
 }
 
 __device__ __forceinline__ float3 sub3(float4 a, float4 b) {
